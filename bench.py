@@ -1,0 +1,142 @@
+"""Throughput benchmark of the FoE Poisson denoiser on one MI355X.
+
+One step = one fe_denoise call over the FP32 baseline workload: one 512 x 512
+synthetic clean image at peaks 1, 2, 4, 8 (four noisy images), 48 zero-mean
+7 x 7 filters, 200 iPiano iterations each, symmetric boundary, data term by
+peak (eq. 3.7).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line:  value = whole-step Mpixel-iterations per second,
+plus images/s, the roofline of the dominant kernel and the FP64 oracle
+timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FoE step Mpixel-iter/s vs roofline; served images/s + p50/p99 latency"
+FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 (matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_per_px_it(m, nf):
+    """Algorithmic contraction flops of one pixel-iteration: the forward and
+    adjoint filter banks, 2 * 2 * N_f * m^2 (a multiply and an add per tap)."""
+    return 4 * nf * m * m
+
+
+def hbm_bytes_per_px_it():
+    """Algorithmic HBM bytes of one pixel-iteration in FP32: read u^n,
+    u^{n-1} and the counts y, write u^{n+1}."""
+    return 16
+
+
+def cpu_baseline(args, k, a, job, tau, gamma):
+    import oracle
+    threads = oracle.set_threads(len(os.sched_getaffinity(0)))
+    _, y = job.arrays()
+    its = args.cpu_iters
+    t0 = time.perf_counter()
+    oracle.denoise(y, k, a, job.lam, tau, gamma, its, job.data_term)
+    dt = time.perf_counter() - t0
+    px_it = job.height * job.width * its
+    return {"value": px_it / dt / 1e6, "unit": "Mpixel-iter/s", "cores": threads,
+            "kind": "oracle", "seconds": dt,
+            "sample": "one %dx%d image (peak %g), %d iterations, %d %dx%d filters, FP64"
+                      % (job.height, job.width, job.peak, its, k.shape[0], k.shape[1],
+                         k.shape[2])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--iterations", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the denoiser's images are independent "
+              "and this build runs no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1609_05722_amd as fe
+    from synth.workloads import fp32_config, prior_for, step_size_for
+
+    cfg = fp32_config(size=args.size, iterations=args.iterations)
+    m, nf = cfg["m"], cfg["n_filters"]
+    k, a = prior_for(m, nf)
+    tau, gamma = step_size_for(m, nf)
+    prior = fe.Prior(k, a, device=0)
+    specs = []
+    for j in cfg["jobs"]:
+        _, y = j.arrays()
+        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), j.lam, j.iterations, tau,
+                                gamma, data_term=j.data_term, peak=j.peak))
+    arr, keep = fe.make_jobs(specs)
+    n = len(specs)
+    ws = fe.alloc_workspace(fe.workspace_size(prior, arr, n), "cuda")
+    stream = torch.cuda.current_stream()
+    lib = fe.library()
+
+    def step():
+        st = lib.fe_denoise(prior.handle, arr, n, fe._ptr(ws), ws.numel(),
+                            fe._stream_handle(stream))
+        if st != 0:
+            raise fe.FeError(st, lib.fe_last_error().decode())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    px_it = sum(j.height * j.width * j.iterations for j in cfg["jobs"])
+    value = px_it / (ms_per_step * 1e-3) / 1e6
+    launches = sum(j.iterations for j in cfg["jobs"])
+    achieved = flops_per_px_it(m, nf) * px_it / (ms_per_step * 1e-3) / 1e12
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel-iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fp32 baseline: %dx%d synthetic image at peaks 1,2,4,8 "
+                               "(4 jobs), %d 7x7 filters, %d iterations"
+                               % (args.size, args.size, nf, args.iterations),
+                   "images_per_step": n, "iterations": args.iterations,
+                   "filters": "%dx%dx%d" % (nf, m, m)},
+        "images_per_s": round(n / (ms_per_step * 1e-3), 2),
+        "wall_s": round(wall, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "whole step (all launches of one fe_denoise call)",
+                     "launches_per_step": launches},
+        "hbm_algorithmic_GBs": round(hbm_bytes_per_px_it() * px_it / (ms_per_step * 1e-3) / 1e9, 1),
+    }
+    if not args.no_cpu:
+        job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
+        result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

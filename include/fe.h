@@ -1,0 +1,137 @@
+/*
+ * fe.h -- C ABI of the MI355X (gfx950) Fields-of-Experts Poisson denoiser.
+ *
+ * The library runs the inference scheme of Feng, Qiao & Chen, "Poisson Noise
+ * Reduction with Higher-order Natural Image Prior Model", eq. 3.7:
+ *
+ *   v      = f_A(y) = 2 sqrt(y + 3/8)                         (eq. 2.3)
+ *   u^0    = u^{-1} = v
+ *   u~     = u^n - tau * grad F(u^n) + gamma * (u^n - u^{n-1}) (eq. 2.8)
+ *            grad F(u) = sum_i alpha_i K_i^T rho'(K_i u),
+ *            rho'(z) = 2z / (1 + z^2)                          (eq. 3.2, 2.6)
+ *   u^{n+1} = prox_{tau G}(u~)                                 (eq. 2.9)
+ *            quadratic G = lambda/2 |u - v|^2:
+ *              (u~ + tau lambda v) / (1 + tau lambda)          (eq. 3.5)
+ *            I-divergence G = lambda <u - v log u, 1>:
+ *              (u~ - tau lambda + sqrt((u~ - tau lambda)^2
+ *                                      + 4 tau lambda v)) / 2  (eq. 3.3, 3.6)
+ *   x_hat  = I_C(u^N)                                          (eq. 2.4)
+ *
+ * K_i is correlation with the m x m taps k_i[a][b] at offset (a - r, b - r),
+ * r = (m - 1) / 2, of the half-sample symmetric extension of the image
+ * (u(-1-i) = u(i)); K_i^T is its exact transpose (ghost contributions are
+ * folded back onto the pixels they mirror).  I_C is applied for
+ * u >= sqrt(3/2), where it is exactly zero, and x_hat = 0 below.
+ *
+ * Conventions for every entry point:
+ *   - every call returns fe_status; FE_OK == 0;
+ *   - arguments are validated on the host before anything is enqueued; on
+ *     error nothing is enqueued and fe_last_error() (thread-local) holds a
+ *     message;
+ *   - image buffers are row-major float32 on the device, owned by the
+ *     caller; the library never frees caller memory and never allocates
+ *     per call: scratch comes from the caller's workspace;
+ *   - work is enqueued asynchronously on the caller's HIP stream
+ *     (hipStream_t passed as void*, NULL = the null stream); a device fault
+ *     is reported as FE_ERR_DEVICE by a later call or by the caller's own
+ *     synchronisation;
+ *   - an fe_ctx is immutable after fe_create and may be used from several
+ *     threads and streams at once, each with its own workspace.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fe_ctx fe_ctx;
+
+typedef int32_t fe_status;
+#define FE_OK 0
+#define FE_ERR_INVALID 1     /* bad argument (shape, NULL, range, workspace) */
+#define FE_ERR_UNSUPPORTED 2 /* valid but not built (filter size, count)     */
+#define FE_ERR_NOMEM 3       /* device allocation in fe_create failed        */
+#define FE_ERR_DEVICE 4      /* HIP runtime reported an error                */
+
+/* Data term selection (eq. 3.7). */
+#define FE_DATA_AUTO 0      /* by job.peak: peak >= 5 quadratic, else I-div */
+#define FE_DATA_QUADRATIC 1 /* eq. 3.4 / 3.5                                */
+#define FE_DATA_IDIV 2      /* eq. 3.6 / 3.3                                */
+
+/* Arithmetic of the filter-bank contractions (K_i u and K_i^T psi).  The
+ * influence, the inertial step, the prox and I_C are FP32 in every mode. */
+#define FE_PREC_FP32 0
+#define FE_PREC_BF16 1 /* bf16 operands, fp32 accumulation */
+#define FE_PREC_FP16 2 /* fp16 operands, fp32 accumulation */
+
+/* The learned prior of eq. 2.5: N_f filters of m x m taps with weights. */
+typedef struct {
+    int32_t m;            /* odd filter side: 3, 5 or 7                      */
+    int32_t n_filters;    /* N_f, 1..64                                      */
+    const float *filters; /* HOST [n_filters][m][m] correlation taps, copied */
+    const float *weights; /* HOST [n_filters] alpha_i >= 0, copied           */
+} fe_prior;
+
+/* One denoising job (one noisy image). */
+typedef struct {
+    int32_t height, width;  /* each >= r = (m - 1) / 2                     */
+    const float *counts;    /* DEVICE H*W, y >= 0, integer valued          */
+    float *out;             /* DEVICE H*W, x_hat = I_C(u_hat); may be NULL */
+    float *out_anscombe;    /* DEVICE H*W, u_hat (Anscombe domain) or NULL */
+    float lambda;           /* data-term weight, > 0                        */
+    int32_t iterations;     /* >= 0; 0 gives x_hat = I_C(f_A(y))            */
+    int32_t data_term;      /* FE_DATA_*                                    */
+    float peak;             /* noise level, used only with FE_DATA_AUTO     */
+    float tau;              /* iPiano step, > 0                             */
+    float gamma;            /* iPiano inertia, 0 <= gamma < 1               */
+    int32_t precision;      /* FE_PREC_*                                    */
+} fe_job;
+
+/* Create a context on HIP device `device`: uploads the filter bank in the
+ * layouts the kernels use.  *out receives the context (NULL on error). */
+fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out);
+
+/* Workspace bytes fe_denoise needs for this batch of jobs (the image state
+ * u^n, u^{n-1} of every job, plus the launch plan). */
+fe_status fe_workspace_size(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
+                            size_t *bytes);
+
+/* Denoise n jobs (eq. 3.7) on `hip_stream`.  The workspace (DEVICE, at
+ * least fe_workspace_size bytes, 256-byte aligned) must not be used by
+ * another call until the stream has passed this one.  Every job's result
+ * is written to its out / out_anscombe buffers.  Asynchronous. */
+fe_status fe_denoise(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Workspace bytes fe_energy_grad needs for an H x W image. */
+fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,
+                                        int32_t width, size_t *bytes);
+
+/* Energy E(u) = E_FoE(u) + D(u, v) (eq. 2.5 with eq. 3.4 or 3.6) and its
+ * gradient, at an Anscombe-domain image u (DEVICE H*W) for counts y
+ * (DEVICE H*W, v = f_A(y)).  data_term is FE_DATA_QUADRATIC or
+ * FE_DATA_IDIV.  If `energy` (HOST) is not NULL the call synchronises the
+ * stream and stores E there; with the I-divergence term E is +inf when any
+ * u <= 0.  If `grad` (DEVICE H*W) is not NULL it receives grad E.  Sums are
+ * accumulated in FP32 per workgroup and combined in FP64 in a fixed order,
+ * so the result is deterministic. */
+fe_status fe_energy_grad(const fe_ctx *ctx, int32_t height, int32_t width,
+                         const float *counts, const float *u, float lambda,
+                         int32_t data_term, double *energy, float *grad,
+                         void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Release the context (NULL is allowed). */
+void fe_destroy(fe_ctx *ctx);
+
+/* Message for the last non-OK status on the calling thread. */
+const char *fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

@@ -1,0 +1,65 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// the gfx950 FoE Poisson denoiser.  Not part of the public ABI (include/fe.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fe {
+
+constexpr int kMaxM = 7;         // largest filter side built
+constexpr int kMaxFilters = 64;  // largest filter count built
+
+// Per-job iteration parameters as the kernels consume them.
+struct StepParams {
+    float tau;        // iPiano step
+    float gamma;      // iPiano inertia
+    float tau_lambda; // tau * lambda, the prox weight
+    int data_term;    // FE_DATA_QUADRATIC or FE_DATA_IDIV
+};
+
+// Filter bank on the device, in the layouts the kernels read.
+struct DeviceBank {
+    int m = 0, nf = 0;
+    float *taps = nullptr;     // [nf][m*m] correlation taps
+    float *alpha2 = nullptr;   // [nf] 2 * alpha_i (the influence's factor)
+    float *alpha = nullptr;    // [nf] alpha_i
+    // MFMA operand tables, one float per lane per register slot (see the
+    // fused step kernel for the exact lane layout).
+    float *mfma_fwd = nullptr; // forward  A operands
+    float *mfma_adj = nullptr; // adjoint  B operands
+    float *mfma_last = nullptr;// the tap left over after groups of four
+    int nfb = 0;               // filter blocks of 16 (zero-padded)
+};
+
+// ---- elementwise kernels (kernels_pointwise.hip) --------------------------
+hipError_t launch_anscombe_init(const float *counts, float *u0, float *u1,
+                                long n, hipStream_t s);
+hipError_t launch_inverse_anscombe(const float *u, float *out,
+                                   float *out_anscombe, long n, hipStream_t s);
+
+// ---- direct (non-MFMA) FP32 kernels (kernels_direct.hip) ------------------
+// psi_i = alpha_i rho'(K_i u) for all filters, written as nf planes of H*W.
+// If rho_partial != NULL every block also writes its FP32 partial sum of
+// alpha_i rho(K_i u) (and data_partial the data-term sum when counts != NULL).
+hipError_t launch_direct_forward(const DeviceBank &bank, const float *u,
+                                 int H, int W, float *psi,
+                                 float *rho_partial, float *data_partial,
+                                 const float *counts, float lambda,
+                                 int data_term, int *n_blocks, hipStream_t s);
+// u_next = prox(u - tau * sum_i K_i^T psi_i + gamma (u - u_prev)); u_next may
+// alias u_prev (each pixel is read before it is written by one thread).
+hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
+                                      const float *u, const float *u_prev,
+                                      const float *counts, float *u_next,
+                                      int H, int W, StepParams p,
+                                      hipStream_t s);
+// grad = sum_i K_i^T psi_i + grad D(u, v).
+hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,
+                                      const float *u, const float *counts,
+                                      float *grad, int H, int W, float lambda,
+                                      int data_term, hipStream_t s);
+int direct_forward_blocks(int H, int W);
+
+}  // namespace fe

@@ -1,0 +1,66 @@
+// Pointwise arithmetic of the denoiser, shared by the FP32 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define FE_DATA_QUADRATIC_ 1
+#define FE_DATA_IDIV_ 2
+
+namespace fe {
+
+// eq. 2.3
+__device__ __forceinline__ float anscombe(float y) { return 2.0f * sqrtf(y + 0.375f); }
+
+// alpha_i rho'(z) with rho(z) = log(1 + z^2) (eq. 2.6): 2 alpha_i z / (1 + z^2);
+// `alpha2` holds 2 alpha_i.
+__device__ __forceinline__ float influence(float z, float alpha2)
+{
+    return alpha2 * z / fmaf(z, z, 1.0f);
+}
+
+// Same with the hardware reciprocal (about 1 ulp) instead of a division.
+__device__ __forceinline__ float influence_fast(float z, float alpha2)
+{
+    return alpha2 * z * __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f));
+}
+
+// Explicit part of the iPiano step (eq. 2.8): u - tau g + gamma (u - u_prev).
+__device__ __forceinline__ float inertial_step(float u, float u_prev, float g,
+                                               float tau, float gamma)
+{
+    return fmaf(-tau, g, u) + gamma * (u - u_prev);
+}
+
+// Proximal map of tau G (eq. 2.9).  tl = tau * lambda.
+//  quadratic (eq. 3.5):   (u~ + tl v) / (1 + tl)
+//  I-divergence (eq. 3.3 with y -> v, eq. 3.6):
+//     (a + sqrt(a^2 + 4 tl v)) / 2,  a = u~ - tl;
+//  for a < 0 the algebraically equal 2 tl v / (sqrt(a^2 + 4 tl v) - a)
+//  avoids the cancellation of a + sqrt(...).
+__device__ __forceinline__ float prox(float ut, float v, float tl, int data_term)
+{
+    if (data_term == FE_DATA_QUADRATIC_) return (ut + tl * v) / (1.0f + tl);
+    const float a = ut - tl;
+    const float c = 4.0f * tl * v;
+    const float s = sqrtf(fmaf(a, a, c));
+    return a >= 0.0f ? 0.5f * (a + s) : (2.0f * tl * v) / (s - a);
+}
+
+// Data-term energy per pixel without the lambda factor:
+//  quadratic 1/2 (u - v)^2; I-divergence u - v log u (+inf for u <= 0).
+__device__ __forceinline__ float data_energy(float u, float v, int data_term)
+{
+    if (data_term == FE_DATA_QUADRATIC_) {
+        const float d = u - v;
+        return 0.5f * d * d;
+    }
+    return u > 0.0f ? u - v * logf(u) : __builtin_inff();
+}
+
+// Gradient of the data term without the lambda factor.
+__device__ __forceinline__ float data_gradient(float u, float v, int data_term)
+{
+    return data_term == FE_DATA_QUADRATIC_ ? u - v : 1.0f - v / u;
+}
+
+}  // namespace fe

@@ -1,0 +1,369 @@
+// Host runtime behind include/fe.h: argument validation, workspace layout,
+// filter-bank upload and the launch sequence of the denoising scheme
+// (eq. 3.7: Anscombe transform, iPiano iterations, closed-form inverse).
+#include "fe.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fe_internal.h"
+#include "fe_plan.h"
+
+struct fe_ctx {
+    int device = 0;
+    int m = 0, nf = 0;
+    std::vector<float> taps, alpha;  // host copies
+    fe::DeviceBank bank;
+    fe::FusedBank fused;             // matrix-core operand tables
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+fe_status fail(fe_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+fe_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(FE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Keeps the caller's current device across a call.
+struct DeviceGuard {
+    int saved = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&saved) != hipSuccess) saved = -1;
+        if (saved != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (saved >= 0 && hipGetDevice(&cur) == hipSuccess && cur != saved)
+            (void)hipSetDevice(saved);
+    }
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int radius(const fe_ctx *c) { return (c->m - 1) / 2; }
+
+int resolve_data_term(const fe_job &j)
+{
+    if (j.data_term == FE_DATA_AUTO) return j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV;
+    return j.data_term;
+}
+
+fe_status check_job(const fe_ctx *c, const fe_job &j, int idx)
+{
+    const int r = radius(c);
+    if (j.height < 1 || j.width < 1 || j.height < r || j.width < r)
+        return fail(FE_ERR_INVALID, "job %d: image %dx%d smaller than the filter radius %d",
+                    idx, j.height, j.width, r);
+    if ((long long)j.height * j.width > (1LL << 31) - 1)
+        return fail(FE_ERR_INVALID, "job %d: image too large", idx);
+    if (!j.counts) return fail(FE_ERR_INVALID, "job %d: counts is NULL", idx);
+    if (!(j.lambda > 0.0f) || !std::isfinite(j.lambda))
+        return fail(FE_ERR_INVALID, "job %d: lambda must be finite and > 0", idx);
+    if (!(j.tau > 0.0f) || !std::isfinite(j.tau))
+        return fail(FE_ERR_INVALID, "job %d: tau must be finite and > 0", idx);
+    if (!(j.gamma >= 0.0f && j.gamma < 1.0f))
+        return fail(FE_ERR_INVALID, "job %d: gamma must be in [0, 1)", idx);
+    if (j.iterations < 0) return fail(FE_ERR_INVALID, "job %d: negative iteration count", idx);
+    if (j.data_term != FE_DATA_AUTO && j.data_term != FE_DATA_QUADRATIC &&
+        j.data_term != FE_DATA_IDIV)
+        return fail(FE_ERR_INVALID, "job %d: unknown data term %d", idx, j.data_term);
+    if (j.data_term == FE_DATA_AUTO && !std::isfinite(j.peak))
+        return fail(FE_ERR_INVALID, "job %d: peak must be finite with FE_DATA_AUTO", idx);
+    if (j.precision != FE_PREC_FP32 && j.precision != FE_PREC_BF16 &&
+        j.precision != FE_PREC_FP16)
+        return fail(FE_ERR_INVALID, "job %d: unknown precision %d", idx, j.precision);
+    if (j.precision != FE_PREC_FP32 && !fe::fused_supported(c->m, c->nf))
+        return fail(FE_ERR_UNSUPPORTED, "job %d: reduced precision needs the matrix-core step", idx);
+    return FE_OK;
+}
+
+fe_status check_batch(const fe_ctx *c, const fe_job *jobs, int32_t n)
+{
+    if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(FE_ERR_INVALID, "negative job count");
+    if (n > 0 && !jobs) return fail(FE_ERR_INVALID, "jobs is NULL");
+    for (int i = 0; i < n; ++i) {
+        fe_status st = check_job(c, jobs[i], i);
+        if (st != FE_OK) return st;
+    }
+    return FE_OK;
+}
+
+// Workspace of fe_denoise: [plan][u planes of job 0][job 1]...[psi scratch]
+struct DenoiseLayout {
+    size_t plan_off = 0, plan_bytes = 0;
+    std::vector<size_t> state_off;  // two planes per job
+    size_t psi_off = 0, psi_bytes = 0;
+    size_t total = 0;
+};
+
+bool use_fused(const fe_ctx *c) { return fe::fused_supported(c->m, c->nf); }
+
+DenoiseLayout layout_for(const fe_ctx *c, const fe_job *jobs, int32_t n,
+                         const fe::Plan *plan)
+{
+    DenoiseLayout L;
+    size_t off = 0;
+    if (plan) {
+        L.plan_off = off;
+        L.plan_bytes = align256(plan->device_bytes());
+        off += L.plan_bytes;
+    }
+    size_t max_plane = 0;
+    L.state_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t plane = (size_t)jobs[i].height * jobs[i].width * sizeof(float);
+        L.state_off[i] = off;
+        off += 2 * align256(plane);
+        max_plane = std::max(max_plane, plane);
+    }
+    if (!use_fused(c)) {
+        L.psi_off = off;
+        L.psi_bytes = align256(max_plane * c->nf);
+        off += L.psi_bytes;
+    }
+    L.total = std::max<size_t>(off, 256);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fe_last_error(void) { return g_error.c_str(); }
+
+fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out)
+{
+    if (!out) return fail(FE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!prior || !prior->filters || !prior->weights)
+        return fail(FE_ERR_INVALID, "prior, filters and weights must be non-NULL");
+    const int m = prior->m, nf = prior->n_filters;
+    if (m != 3 && m != 5 && m != 7)
+        return fail(FE_ERR_UNSUPPORTED, "filter side %d not built (3, 5, 7)", m);
+    if (nf < 1 || nf > fe::kMaxFilters)
+        return fail(FE_ERR_UNSUPPORTED, "filter count %d outside 1..%d", nf, fe::kMaxFilters);
+    for (int i = 0; i < nf; ++i)
+        if (!(prior->weights[i] >= 0.0f) || !std::isfinite(prior->weights[i]))
+            return fail(FE_ERR_INVALID, "weight %d must be finite and >= 0", i);
+    for (int i = 0; i < nf * m * m; ++i)
+        if (!std::isfinite(prior->filters[i]))
+            return fail(FE_ERR_INVALID, "filter tap %d is not finite", i);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(FE_ERR_INVALID, "device %d not available", device);
+
+    fe_ctx *c = new (std::nothrow) fe_ctx;
+    if (!c) return fail(FE_ERR_NOMEM, "host allocation failed");
+    c->device = device;
+    c->m = m;
+    c->nf = nf;
+    c->taps.assign(prior->filters, prior->filters + (size_t)nf * m * m);
+    c->alpha.assign(prior->weights, prior->weights + nf);
+
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) {
+        delete c;
+        return hip_fail(g.err, "hipSetDevice");
+    }
+    std::vector<float> a2(nf);
+    for (int i = 0; i < nf; ++i) a2[i] = 2.0f * c->alpha[i];
+    fe::DeviceBank &b = c->bank;
+    b.m = m;
+    b.nf = nf;
+    hipError_t e = hipMalloc((void **)&b.taps, sizeof(float) * nf * m * m);
+    if (e == hipSuccess) e = hipMalloc((void **)&b.alpha2, sizeof(float) * nf);
+    if (e == hipSuccess) e = hipMalloc((void **)&b.alpha, sizeof(float) * nf);
+    if (e == hipSuccess)
+        e = hipMemcpy(b.taps, c->taps.data(), sizeof(float) * nf * m * m, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.alpha2, a2.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b.alpha, c->alpha.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
+    if (e == hipSuccess && use_fused(c))
+        e = fe::fused_upload(c->taps.data(), c->alpha.data(), m, nf, &c->fused);
+    if (e != hipSuccess) {
+        fe_status st = e == hipErrorOutOfMemory ? fail(FE_ERR_NOMEM, "device allocation failed")
+                                                : hip_fail(e, "fe_create upload");
+        fe_destroy(c);
+        return st;
+    }
+    *out = c;
+    return FE_OK;
+}
+
+void fe_destroy(fe_ctx *c)
+{
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipFree(c->bank.taps);
+    (void)hipFree(c->bank.alpha2);
+    (void)hipFree(c->bank.alpha);
+    fe::fused_release(&c->fused);
+    delete c;
+}
+
+fe_status fe_workspace_size(const fe_ctx *c, const fe_job *jobs, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    fe_status st = check_batch(c, jobs, n);
+    if (st != FE_OK) return st;
+    fe::Plan plan;
+    const bool fused = use_fused(c);
+    if (fused) fe::make_plan(c->m, jobs, n, &plan);
+    *bytes = layout_for(c, jobs, n, fused ? &plan : nullptr).total;
+    return FE_OK;
+}
+
+fe_status fe_denoise(const fe_ctx *c, const fe_job *jobs, int32_t n,
+                     void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st != FE_OK) return st;
+    if (n == 0) return FE_OK;
+    const bool fused = use_fused(c);
+    fe::Plan plan;
+    if (fused) fe::make_plan(c->m, jobs, n, &plan);
+    DenoiseLayout L = layout_for(c, jobs, n, fused ? &plan : nullptr);
+    if (!workspace) return fail(FE_ERR_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(FE_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *ws = (char *)workspace;
+
+    std::vector<float *> ua(n), ub(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t plane = align256((size_t)jobs[i].height * jobs[i].width * sizeof(float));
+        ua[i] = (float *)(ws + L.state_off[i]);
+        ub[i] = (float *)(ws + L.state_off[i] + plane);
+        hipError_t e = fe::launch_anscombe_init(jobs[i].counts, ua[i], ub[i],
+                                                (long)jobs[i].height * jobs[i].width, s);
+        if (e != hipSuccess) return hip_fail(e, "anscombe init");
+    }
+
+    if (fused) {
+        hipError_t e = fe::run_fused(c->fused, plan, jobs, n, ua.data(), ub.data(),
+                                     ws + L.plan_off, s);
+        if (e != hipSuccess) return hip_fail(e, "fused step");
+        // run_fused leaves every job's last iterate in ua[i]
+    } else {
+        float *psi = (float *)(ws + L.psi_off);
+        for (int i = 0; i < n; ++i) {
+            const fe_job &j = jobs[i];
+            fe::StepParams p{j.tau, j.gamma, j.tau * j.lambda, resolve_data_term(j)};
+            for (int it = 0; it < j.iterations; ++it) {
+                hipError_t e = fe::launch_direct_forward(c->bank, ua[i], j.height, j.width, psi,
+                                                         nullptr, nullptr, nullptr, 0.0f, 0,
+                                                         nullptr, s);
+                if (e == hipSuccess)
+                    e = fe::launch_direct_adjoint_step(c->bank, psi, ua[i], ub[i], j.counts, ub[i],
+                                                       j.height, j.width, p, s);
+                if (e != hipSuccess) return hip_fail(e, "direct step");
+                std::swap(ua[i], ub[i]);
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = fe::launch_inverse_anscombe(ua[i], jobs[i].out, jobs[i].out_anscombe,
+                                                   (long)jobs[i].height * jobs[i].width, s);
+        if (e != hipSuccess) return hip_fail(e, "inverse anscombe");
+    }
+    return FE_OK;
+}
+
+fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
+    const int r = radius(c);
+    if (H < 1 || W < 1 || H < r || W < r)
+        return fail(FE_ERR_INVALID, "image %dx%d smaller than the filter radius %d", H, W, r);
+    const size_t plane = (size_t)H * W * sizeof(float);
+    const size_t nb = (size_t)fe::direct_forward_blocks(H, W);
+    *bytes = align256(plane * c->nf) + 2 * align256(nb * sizeof(float));
+    return FE_OK;
+}
+
+fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *counts,
+                         const float *u, float lambda, int32_t data_term, double *energy,
+                         float *grad, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    size_t need = 0;
+    fe_status st = fe_energy_grad_workspace_size(c, H, W, &need);
+    if (st != FE_OK) return st;
+    if (!counts || !u) return fail(FE_ERR_INVALID, "counts and u must be non-NULL");
+    if (!(lambda > 0.0f) || !std::isfinite(lambda))
+        return fail(FE_ERR_INVALID, "lambda must be finite and > 0");
+    if (data_term != FE_DATA_QUADRATIC && data_term != FE_DATA_IDIV)
+        return fail(FE_ERR_INVALID, "data term must be FE_DATA_QUADRATIC or FE_DATA_IDIV");
+    if (!workspace || ((uintptr_t)workspace & 255))
+        return fail(FE_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < need) return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
+    if (!energy && !grad) return FE_OK;
+
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *ws = (char *)workspace;
+    const size_t plane = (size_t)H * W * sizeof(float);
+    float *psi = (float *)ws;
+    const int nb = fe::direct_forward_blocks(H, W);
+    float *rho_part = (float *)(ws + align256(plane * c->nf));
+    float *data_part = (float *)(ws + align256(plane * c->nf) + align256(nb * sizeof(float)));
+    int nblocks = 0;
+    hipError_t e = fe::launch_direct_forward(c->bank, u, H, W, psi, energy ? rho_part : nullptr,
+                                             energy ? data_part : nullptr, counts, lambda,
+                                             data_term, &nblocks, s);
+    if (e != hipSuccess) return hip_fail(e, "energy forward");
+    if (grad) {
+        e = fe::launch_direct_adjoint_grad(c->bank, psi, u, counts, grad, H, W, lambda,
+                                           data_term, s);
+        if (e != hipSuccess) return hip_fail(e, "energy adjoint");
+    }
+    if (energy) {
+        std::vector<float> hr(nblocks), hd(nblocks);
+        e = hipMemcpyAsync(hr.data(), rho_part, sizeof(float) * nblocks, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hd.data(), data_part, sizeof(float) * nblocks,
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "energy readback");
+        double sum = 0.0;
+        for (int b = 0; b < nblocks; ++b) sum += (double)hr[b];
+        for (int b = 0; b < nblocks; ++b) sum += (double)hd[b];
+        *energy = sum;
+    }
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+function declared in include/*.h is exported, and argument errors are
+reported before anything touches a device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(fe_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1609_05722_amd as fe
+    return fe.library()
+
+
+def test_header_declares_the_abi():
+    names = _declared()
+    for n in ("fe_create", "fe_denoise", "fe_energy_grad", "fe_destroy",
+              "fe_workspace_size", "fe_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in sorted(_declared()):
+        assert hasattr(lib, name), name
+
+
+def test_binding_lists_every_export():
+    import paper_1609_05722_amd as fe
+    assert set(fe.EXPORTS) == _declared()
+
+
+def _prior_struct(fe, m, nf):
+    f = np.zeros((nf, m, m), np.float32)
+    w = np.ones(nf, np.float32)
+    pr = fe._Prior(m, nf, f.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return pr, (f, w)
+
+
+def test_create_rejects_bad_priors(lib):
+    import paper_1609_05722_amd as fe
+    h = ctypes.c_void_p()
+    for m, nf, status in ((4, 8, fe.FE_ERR_UNSUPPORTED), (9, 8, fe.FE_ERR_UNSUPPORTED),
+                          (7, 0, fe.FE_ERR_UNSUPPORTED), (7, 65, fe.FE_ERR_UNSUPPORTED)):
+        pr, keep = _prior_struct(fe, m, nf)
+        assert lib.fe_create(ctypes.byref(pr), 0, ctypes.byref(h)) == status
+        assert h.value is None
+        assert len(lib.fe_last_error()) > 0
+    assert lib.fe_create(None, 0, ctypes.byref(h)) == fe.FE_ERR_INVALID
+    pr, keep = _prior_struct(fe, 7, 48)
+    keep[1][3] = -1.0
+    assert lib.fe_create(ctypes.byref(pr), 0, ctypes.byref(h)) == fe.FE_ERR_INVALID
+    keep[1][3] = 1.0
+    keep[0][2, 1, 1] = np.nan
+    assert lib.fe_create(ctypes.byref(pr), 0, ctypes.byref(h)) == fe.FE_ERR_INVALID
+
+
+def test_create_rejects_missing_device(lib):
+    import paper_1609_05722_amd as fe
+    pr, keep = _prior_struct(fe, 7, 48)
+    h = ctypes.c_void_p()
+    assert lib.fe_create(ctypes.byref(pr), 1 << 20, ctypes.byref(h)) == fe.FE_ERR_INVALID
+
+
+def test_null_context_is_rejected(lib):
+    import paper_1609_05722_amd as fe
+    sz = ctypes.c_size_t()
+    assert lib.fe_workspace_size(None, None, 0, ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    assert lib.fe_denoise(None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
+    assert lib.fe_energy_grad_workspace_size(None, 8, 8, ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    lib.fe_destroy(None)  # NULL-safe

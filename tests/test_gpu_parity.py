@@ -1,0 +1,162 @@
+"""Parity of the gfx950 library (through the C ABI) with the FP64 oracle.
+
+Tolerance: the FP32 GPU path must match the FP64 oracle within 1e-4
+relative per pixel, |gpu - oracle| <= 1e-4 * max(|oracle|, 1), for both the
+Anscombe-domain result u_hat and x_hat = I_C(u_hat).  The floor of 1 keeps
+dark pixels, where x_hat is legitimately 0 or tiny, on an absolute 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_prior, noisy_pair
+from synth.workloads import (IDIV, QUADRATIC, fp32_config, oracle_config,
+                             prior_for, step_size_for)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def fe(torch):
+    import paper_1609_05722_amd as fe
+    fe.library()
+    return fe
+
+
+_PRIORS = {}
+
+
+def _prior(fe, m, nf):
+    key = (m, nf)
+    if key not in _PRIORS:
+        k, a = prior_for(m, nf)
+        _PRIORS[key] = (fe.Prior(k, a), k, a)
+    return _PRIORS[key]
+
+
+def _run(fe, torch, prior, y, lam, tau, gamma, iters, data_term, precision="fp32"):
+    c = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
+    x, u = fe.denoise(c, prior, lam, iters, tau, gamma, data_term=data_term,
+                      precision=precision, want_anscombe=True)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.float64), x.cpu().numpy().astype(np.float64)
+
+
+def _rel_err(a, ref):
+    return np.max(np.abs(a - ref) / np.maximum(np.abs(ref), 1.0))
+
+
+def _check(fe, torch, m, nf, y, lam, tau, gamma, iters, data_term, tol=TOL):
+    prior, k, a = _prior(fe, m, nf)
+    print("case H=%d W=%d m=%d nf=%d iters=%d dt=%d" % (y.shape + (m, nf, iters, data_term)),
+          flush=True)
+    ug, xg = _run(fe, torch, prior, y, lam, tau, gamma, iters, data_term)
+    uo, xo = oracle.denoise(y, k, a, lam, tau, gamma, iters, data_term)
+    eu, ex = _rel_err(ug, uo), _rel_err(xg, xo)
+    assert eu <= tol and ex <= tol, (eu, ex)
+    return eu, ex
+
+
+def test_oracle_size_config(fe, torch):
+    """64 x 64 at peak 4, 24 filters of 5 x 5, 100 iterations (I-div)."""
+    cfg = oracle_config()
+    j = cfg["jobs"][0]
+    tau, gamma = step_size_for(5, 24)
+    _, y = j.arrays()
+    _check(fe, torch, 5, 24, y, j.lam, tau, gamma, j.iterations, j.data_term)
+
+
+@pytest.mark.parametrize("data_term", [QUADRATIC, IDIV])
+@pytest.mark.parametrize("shape", [(8, 8), (37, 53), (3, 3), (5, 200), (130, 67)])
+def test_small_shapes(fe, torch, shape, data_term):
+    """Several tiles with ragged tails, the H = W = r minimum, thin strips."""
+    H, W = shape
+    tau, gamma = step_size_for(7, 48)
+    x, y = noisy_pair(40 + H, 60 + W, H, W, 3.0)
+    _check(fe, torch, 7, 48, y, 50.0, tau, gamma, 30, data_term)
+
+
+def test_zero_iterations_is_inverse_of_anscombe(fe, torch):
+    tau, gamma = step_size_for(7, 48)
+    x, y = noisy_pair(5, 6, 33, 47, 2.0)
+    prior, k, a = _prior(fe, 7, 48)
+    ug, xg = _run(fe, torch, prior, y, 10.0, tau, gamma, 0, IDIV)
+    v = oracle.anscombe(y)
+    assert _rel_err(ug, v) <= 1e-6
+    assert _rel_err(xg, oracle.inverse_anscombe(v)) <= 1e-5
+
+
+@pytest.mark.parametrize("data_term", [QUADRATIC, IDIV])
+def test_zero_weights_keep_v(fe, torch, data_term):
+    k, a = prior_for(7, 48)
+    prior = fe.Prior(k, np.zeros_like(a))
+    tau, gamma = step_size_for(7, 48)
+    x, y = noisy_pair(7, 8, 40, 45, 4.0)
+    ug, _ = _run(fe, torch, prior, y, 30.0, tau, gamma, 50, data_term)
+    assert _rel_err(ug, oracle.anscombe(y)) <= 1e-5
+
+
+def test_full_size_peak4_idiv(fe, torch):
+    """512 x 512 at peak 4 (I-div branch), 48 filters of 7 x 7, 200 its."""
+    cfg = fp32_config()
+    j = [jj for jj in cfg["jobs"] if jj.peak == 4.0][0]
+    tau, gamma = step_size_for(7, 48)
+    _, y = j.arrays()
+    _check(fe, torch, 7, 48, y, j.lam, tau, gamma, j.iterations, j.data_term)
+
+
+def test_full_size_peak8_quadratic(fe, torch):
+    cfg = fp32_config()
+    j = [jj for jj in cfg["jobs"] if jj.peak == 8.0][0]
+    tau, gamma = step_size_for(7, 48)
+    _, y = j.arrays()
+    _check(fe, torch, 7, 48, y, j.lam, tau, gamma, j.iterations, j.data_term)
+
+
+def test_batch_equals_alone_and_is_deterministic(fe, torch):
+    """Jobs of different sizes and data terms in one call give bitwise the
+    same results as each job alone, and repeated runs are bitwise equal."""
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    shapes = [(64, 64, 1.0), (97, 130, 8.0), (20, 300, 2.0), (256, 256, 4.0)]
+    specs, ys = [], []
+    for i, (H, W, pk) in enumerate(shapes):
+        _, y = noisy_pair(300 + i, 400 + i, H, W, pk)
+        ys.append(y)
+        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, 25, tau, gamma,
+                                data_term="auto", peak=pk, want_anscombe=True))
+    mix = fe.denoise_jobs(prior, specs)
+    mix2 = fe.denoise_jobs(prior, specs)
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        (x1, u1), = fe.denoise_jobs(prior, [s])
+        torch.cuda.synchronize()
+        assert torch.equal(u1, mix[i][1]) and torch.equal(x1, mix[i][0])
+        assert torch.equal(mix2[i][1], mix[i][1])
+
+
+@pytest.mark.parametrize("data_term", [QUADRATIC, IDIV])
+def test_energy_and_gradient(fe, torch, data_term):
+    prior, k, a = _prior(fe, 7, 48)
+    x, y = noisy_pair(21, 22, 61, 75, 4.0)
+    v = oracle.anscombe(y)
+    u = v + np.random.default_rng(3).uniform(-0.3, 0.3, v.shape)
+    u32 = u.astype(np.float32)
+    e, g = fe.energy_grad(torch.from_numpy(y).cuda(), torch.from_numpy(u32).cuda(),
+                          prior, 30.0, data_term)
+    eo, go = oracle.energy_grad(u32.astype(np.float64), v, k.astype(np.float64),
+                                a.astype(np.float64), np.float32(30.0), data_term)
+    assert abs(e - eo) <= 1e-5 * abs(eo), (e, eo)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(g - go)) <= 1e-4 * max(np.max(np.abs(go)), 1e-3), \
+        np.max(np.abs(g - go))
