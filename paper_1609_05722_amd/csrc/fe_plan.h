@@ -12,25 +12,24 @@
 
 namespace fe {
 
+constexpr int kMaxTileRows = 128;  // largest tile height a plan may pick
+
 // Matrix-core operand tables of one filter bank (see kernels_fused.hip).
 struct FusedBank {
     int m = 0, nf = 0, nfb = 0;  // nfb: filter blocks of 16 after zero-padding
-    float *fwd = nullptr;        // forward A operands   [kf][nfb][64]
-    float *adj = nullptr;        // adjoint B operands   [nfb][4][ntb][64]
-    float *last = nullptr;       // last tap per filter  [nfb][4][64]
-    float *alpha2 = nullptr;     // 2 alpha per filter   [nfb][4][64]
+    float *fwd = nullptr;        // forward A operands          [kf][nfb][64]
+    float *adj = nullptr;        // adjoint B operands x 2alpha [nfb][4][ntb][64]
+    float *lastf = nullptr;      // last tap, forward           [nfb][4][64]
+    float *lasta = nullptr;      // last tap x 2alpha, adjoint  [nfb][4][64]
 };
 
-// One workgroup's share of an image: output rows [y0, y0 + ty) and
-// columns [x0, x0 + tx) of job `job`.
-struct Tile {
-    int job, y0, x0, ty, tx;
-};
-
+// How a batch is cut into workgroup tiles: every job's image is split into
+// a grid of ntx x nty nearly equal tiles of at most tile_w x tile_h pixels.
 struct Plan {
-    std::vector<Tile> tiles;
     int tile_w = 0, tile_h = 0;
-    size_t device_bytes() const { return tiles.size() * sizeof(Tile); }
+    int njobs = 0, ntiles = 0;
+    std::vector<int> jobs_ntx, jobs_nty;
+    size_t device_bytes() const;  // job table in the workspace
 };
 
 bool fused_supported(int m, int nf);

@@ -1,11 +1,492 @@
-// Fused matrix-core step (placeholder until the kernel lands).
+// Fused iPiano step on the matrix cores (gfx950, FP32 MFMA 16x16x4).
+//
+// One launch performs one iteration of eq. 2.8 for every tile of every job:
+//
+//   z_i  = K_i u^n                          forward filter bank  (MFMA)
+//   phi_i = z_i / (1 + z_i^2)               influence / (2 alpha_i)  (VALU)
+//   g    = sum_i K_i^T (2 alpha_i phi_i)    adjoint filter bank  (MFMA)
+//   u^{n+1} = prox(u^n - tau g + gamma (u^n - u^{n-1}))          (VALU)
+//
+// Tiling.  A workgroup owns an output tile of at most TY x TX pixels.  The
+// adjoint at an output pixel needs psi on the tile grown by r, which needs
+// u on the tile grown by 2r; both grown regions are computed in the
+// workgroup (halo recompute) so that nothing but u^n, u^{n-1} and y crosses
+// HBM.  The psi region is processed as "q-rows" of QW = 16 * QB pixels,
+// one q-row per wave per step, each q-row as QB blocks of 16 pixels:
+//
+//   forward  Z^T[16 filters x 16 px] += A[16 filters x 4 taps] B[4 taps x 16 px]
+//            A: filter taps (registers), B: u gathered from the LDS tile
+//   adjoint  C[16 px x 16 taps] += Phi[16 px x 4 filters] Kt[4 filters x 16 taps]
+//            Phi is the forward accumulator itself: the MFMA output layout
+//            (lane = px + 16 * (filter/4), item = filter%4) is exactly the A
+//            operand layout of the next product with the filter index as
+//            the reduction index, so no data moves between the two.
+//
+// m^2 = 4 k + 1 for odd m, so 4 k taps go through the matrix cores and the
+// last tap through VALU FMAs.  C[p][t] is the contribution of psi at pixel p
+// to the extended position p + (a - r, b - r), t = (a, b).  It is collapsed
+// in two deterministic passes through LDS: horizontally per q-row into
+// H[q-row][a][x] = sum_b C[x - b + r][(a, b)], then vertically per output
+// row, g(y) = sum_a H[y - a + r][a], adding the ghost rows and columns that
+// mirror each border pixel (the transpose of the symmetric extension).
+// No atomics: every sum is taken in a fixed order, so results are bitwise
+// reproducible and independent of what else is in the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fe_internal.h"
+#include "fe_math.h"
 #include "fe_plan.h"
 
 namespace fe {
-bool fused_supported(int, int) { return false; }
-hipError_t fused_upload(const float *, const float *, int, int, FusedBank *) { return hipSuccess; }
-void fused_release(FusedBank *) {}
-void make_plan(int, const fe_job *, int, Plan *) {}
-hipError_t run_fused(const FusedBank &, const Plan &, const fe_job *, int, float **, float **,
-                     void *, hipStream_t) { return hipErrorNotSupported; }
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 8;             // waves per workgroup
+constexpr int kThreads = 64 * kWaves; // 512
+constexpr int kQB = 4;                // 16-pixel blocks per q-row
+constexpr int kQW = 16 * kQB;         // q-row width (pixels)
+
+// Per-job description the step kernel reads.
+struct JobDesc {
+    const float *counts;
+    float *ua, *ub;     // state planes; u^n is ua on even iterations
+    int H, W;
+    int ntx, nty;       // tile grid of this job
+    int tile_base;      // index of the job's first tile in the launch
+    int iters;
+    float tau, gamma, tl;
+    int data_term;
+};
+
+template <int M>
+struct Geo {
+    static constexpr int R = (M - 1) / 2;
+    static constexpr int T = M * M;
+    static constexpr int KF = (T - 1) / 4;            // MFMA k-steps (4 taps each)
+    static constexpr int NTB = (T - 1 + 15) / 16;     // adjoint tap blocks of 16
+    static constexpr int TX = kQW - 2 * R;            // output columns per tile
+    static constexpr int UC = kQW + 2 * R;            // u tile columns
+    static constexpr int US = UC + 2;                 // u tile row stride (floats)
+    static constexpr int SROWS = 16 * NTB + 1;        // scratch rows (taps; last tap last)
+    static constexpr int SPAD = 8;                    // zero columns left of a block
+    static constexpr int SW = 36;                     // scratch row stride (floats)
+    static constexpr int HR = kWaves + 2 * R;         // H ring slots (q-rows)
+    static constexpr int XSPAN = 16 + 2 * R;          // columns one block reaches
+    static constexpr int TASKS = M * XSPAN;           // (a, x) collapse tasks per block
+    static constexpr int ROUNDS = (TASKS + 63) / 64;
+    static constexpr int LAST_ROW = 16 * NTB;         // scratch row of the last tap
+};
+
+template <int M>
+size_t lds_bytes(int ty_max)
+{
+    using G = Geo<M>;
+    return sizeof(float) * ((size_t)(ty_max + 4 * G::R) * G::US +
+                            (size_t)kWaves * G::SROWS * G::SW + (size_t)G::HR * M * kQW);
+}
+
+__device__ __forceinline__ int sym_clamp(int i, int n)
+{
+    if (i < 0) i = -1 - i;
+    if (i >= n) i = 2 * n - 1 - i;
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Orders this wave's LDS writes before its later LDS reads (and vice versa)
+// across lanes: the compiler reasons per lane and could otherwise move them.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int M, int NFB>
+__global__ __launch_bounds__(kThreads)
+void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
+                       const float *__restrict__ fwd_tab,
+                       const float *__restrict__ adj_tab,
+                       const float *__restrict__ lastf_tab,
+                       const float *__restrict__ lasta_tab,
+                       int iter, int ty_max)
+{
+    using G = Geo<M>;
+    constexpr int R = G::R;
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int p = lane & 15;   // pixel within a 16-pixel block
+    const int g = lane >> 4;   // lane group: k index of the MFMA operands
+
+    // ---- locate the tile: jobs are sorted by tile_base --------------------
+    int lo = 0, hi = njobs - 1;
+    const int bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
+    }
+    const JobDesc J = jobs[lo];
+    if (iter >= J.iters) return;
+    const int local = bid - J.tile_base;
+    const int tix = local % J.ntx, tiy = local / J.ntx;
+    if (tiy >= J.nty) return;
+    const int H = J.H, W = J.W;
+    const int x0 = (int)((long)tix * W / J.ntx), x1 = (int)((long)(tix + 1) * W / J.ntx);
+    const int y0 = (int)((long)tiy * H / J.nty), y1 = (int)((long)(tiy + 1) * H / J.nty);
+    const int tx = x1 - x0, ty = y1 - y0;
+    const float *__restrict__ ucur = (iter & 1) ? J.ub : J.ua;
+    float *uprev = (iter & 1) ? J.ua : J.ub;   // u^{n-1}, overwritten by u^{n+1}
+
+    float *U = lds;                                        // (ty_max + 4R) x US
+    float *S = U + (size_t)(ty_max + 4 * R) * G::US;       // kWaves x SROWS x SW
+    float *Hr = S + (size_t)kWaves * G::SROWS * G::SW;     // HR x M x QW
+    float *Sw = S + (size_t)wave * G::SROWS * G::SW;
+
+    // ---- operand tables into registers -----------------------------------
+    float afwd[G::KF][NFB];
+#pragma unroll
+    for (int s = 0; s < G::KF; ++s)
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
+    float badj[NFB][4][G::NTB];
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int nb = 0; nb < G::NTB; ++nb)
+                badj[fb][j][nb] = adj_tab[((fb * 4 + j) * G::NTB + nb) * 64 + lane];
+    float lastf[NFB][4], lasta[NFB][4];
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lastf[fb][j] = lastf_tab[(fb * 4 + j) * 64 + lane];
+            lasta[fb][j] = lasta_tab[(fb * 4 + j) * 64 + lane];
+        }
+    // LDS offsets of the forward B operand: tap 4s + g at pixel p.
+    int boff[G::KF];
+#pragma unroll
+    for (int s = 0; s < G::KF; ++s) {
+        const int t = 4 * s + g;
+        boff[s] = (t / M) * G::US + (t % M) + p;
+    }
+    const int loff = (M - 1) * G::US + (M - 1) + p;  // last tap
+
+    // ---- zero this wave's scratch (its pad columns stay zero) -------------
+    for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
+
+    // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
+    const int urows = ty + 4 * R;
+    for (int i = threadIdx.x; i < urows * G::UC; i += kThreads) {
+        const int ur = i / G::UC, uc = i - ur * G::UC;
+        const int yy = sym_clamp(y0 - 2 * R + ur, H);
+        const int xx = sym_clamp(x0 - 2 * R + uc, W);
+        U[ur * G::US + uc] = ucur[(long)yy * W + xx];
+    }
+    __syncthreads();
+
+    const int nq = ty + 2 * R;                 // q-rows of the tile
+    const int nsteps = (nq + kWaves - 1) / kWaves;
+    for (int st = 0; st < nsteps; ++st) {
+        // ================= q-row: forward, influence, adjoint, collapse =====
+        const int qr = st * kWaves + wave;
+        const int qy = y0 - R + qr;            // image row of this q-row
+        if (qr < nq && qy >= 0 && qy < H) {
+            float *Hs = Hr + (size_t)(qr % G::HR) * M * kQW;
+            for (int k = 0; k < kQB; ++k) {
+                const float *Ub = U + qr * G::US + 16 * k;
+                f32x4 z[NFB];
+#pragma unroll
+                for (int fb = 0; fb < NFB; ++fb) z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < G::KF; ++s) {
+                    const float b = Ub[boff[s]];
+#pragma unroll
+                    for (int fb = 0; fb < NFB; ++fb)
+                        z[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afwd[s][fb], b, z[fb], 0, 0, 0);
+                }
+                const float ul = Ub[loff];
+                const int qx = x0 - R + 16 * k + p;
+                const bool inside = qx >= 0 && qx < W;
+                f32x4 c[G::NTB];
+#pragma unroll
+                for (int nb = 0; nb < G::NTB; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                float part = 0.0f;
+#pragma unroll
+                for (int fb = 0; fb < NFB; ++fb) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float zz = fmaf(lastf[fb][j], ul, z[fb][j]);
+                        const float phi = inside ? zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f)) : 0.0f;
+#pragma unroll
+                        for (int nb = 0; nb < G::NTB; ++nb)
+                            c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
+                        part = fmaf(lasta[fb][j], phi, part);
+                    }
+                }
+                part += __shfl_xor(part, 16);
+                part += __shfl_xor(part, 32);
+                // C[px = 4g + jj][tap = 16 nb + p] -> scratch row = tap, column = px
+#pragma unroll
+                for (int nb = 0; nb < G::NTB; ++nb)
+                    *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
+                if (g == 0) Sw[G::LAST_ROW * G::SW + G::SPAD + p] = part;
+                wave_lds_sync();
+                // horizontal collapse: H[a][16k + xr] (+)= sum_b C[xr + R - b][(a, b)]
+#pragma unroll
+                for (int rr = 0; rr < G::ROUNDS; ++rr) {
+                    const int task = rr * 64 + lane;
+                    if (task < G::TASKS) {
+                        const int a = task / G::XSPAN;
+                        const int xr = task - a * G::XSPAN - R;
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int b = 0; b < M; ++b) {
+                            const int t = a * M + b;
+                            const int row = (t < G::T - 1) ? t : G::LAST_ROW;
+                            acc += Sw[row * G::SW + G::SPAD + xr + R - b];
+                        }
+                        const int x = 16 * k + xr;
+                        if (x >= 0 && x < kQW) {
+                            float *h = Hs + a * kQW + x;
+                            *h = (k > 0 && xr < R) ? *h + acc : acc;
+                        }
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        __syncthreads();
+        // ================= output rows whose q-rows are all done ============
+        const int orow = st * kWaves - 2 * R + wave;
+        if (orow >= 0 && orow < ty && lane < tx) {
+            const int y = y0 + orow, x = x0 + lane;
+            int rows[3], nr = 0;
+            if (y < R) rows[nr++] = -1 - y;
+            rows[nr++] = y;
+            if (y >= H - R) rows[nr++] = 2 * H - 1 - y;
+            const int hx = x - (x0 - R);
+            const int hxl = (x < R) ? (-1 - x) - (x0 - R) : -1;
+            const int hxr = (x >= W - R) ? (2 * W - 1 - x) - (x0 - R) : -1;
+            float gsum = 0.0f;
+            for (int ir = 0; ir < nr; ++ir) {
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    const int qyy = rows[ir] - a + R;
+                    if (qyy < 0 || qyy >= H) continue;
+                    const int q = qyy - (y0 - R);
+                    const float *h = Hr + (size_t)(q % G::HR) * M * kQW + a * kQW;
+                    if (hxl >= 0) gsum += h[hxl];
+                    gsum += h[hx];
+                    if (hxr >= 0) gsum += h[hxr];
+                }
+            }
+            const long pix = (long)y * W + x;
+            const float uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
+            const float ut = inertial_step(uc, uprev[pix], gsum, J.tau, J.gamma);
+            uprev[pix] = prox(ut, anscombe(J.counts[pix]), J.tl, J.data_term);
+        }
+        __syncthreads();
+    }
+}
+
+// Job table upload through kernel arguments (no host-to-device copy, so the
+// call stays asynchronous and capturable).
+constexpr int kChunk = 32;
+struct JobChunk {
+    int first, count;
+    JobDesc d[kChunk];
+};
+
+__global__ void write_jobs_kernel(JobChunk c, JobDesc *dst)
+{
+    const int i = threadIdx.x;
+    if (i < c.count) dst[c.first + i] = c.d[i];
+}
+
+int nfb_for(int nf) { return (nf + 15) / 16; }
+
+template <int M, int NFB>
+hipError_t launch_step(const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
+                       int iter, int ty_max, hipStream_t s)
+{
+    const size_t bytes = lds_bytes<M>(ty_max);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, NFB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes<M>(kMaxTileRows));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    fused_step_kernel<M, NFB><<<ntiles, kThreads, bytes, s>>>(jobs, njobs, b.fwd, b.adj, b.lastf,
+                                                              b.lasta, iter, ty_max);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fused_supported(int m, int nf) { return (m == 3 || m == 5 || m == 7) && nf >= 1 && nf <= 64; }
+
+// Host-side construction of the operand tables (lane layouts of
+// v_mfma_f32_16x16x4_f32: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
+// D[i][j] at lane j + 16 (i / 4), item i % 4).
+hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, FusedBank *out)
+{
+    const int T = m * m, KF = (T - 1) / 4, NTB = (T - 1 + 15) / 16, NFB = nfb_for(nf);
+    auto tap = [&](int f, int t) { return (f < nf && t < T) ? taps[f * T + t] : 0.0f; };
+    auto a2 = [&](int f) { return f < nf ? 2.0f * alpha[f] : 0.0f; };
+    std::vector<float> fwd((size_t)KF * NFB * 64), adj((size_t)NFB * 4 * NTB * 64),
+        lastf((size_t)NFB * 4 * 64), lasta((size_t)NFB * 4 * 64);
+    for (int s = 0; s < KF; ++s)
+        for (int fb = 0; fb < NFB; ++fb)
+            for (int l = 0; l < 64; ++l)  // A[filter = l%16][tap = 4s + l/16]
+                fwd[(s * NFB + fb) * 64 + l] = tap(fb * 16 + (l & 15), 4 * s + (l >> 4));
+    for (int fb = 0; fb < NFB; ++fb)
+        for (int j = 0; j < 4; ++j)
+            for (int nb = 0; nb < NTB; ++nb)
+                for (int l = 0; l < 64; ++l) {  // B[k = filter 4(l/16)+j][tap 16nb + l%16]
+                    const int f = fb * 16 + 4 * (l >> 4) + j, t = nb * 16 + (l & 15);
+                    adj[((fb * 4 + j) * NTB + nb) * 64 + l] = t < T - 1 ? a2(f) * tap(f, t) : 0.0f;
+                }
+    for (int fb = 0; fb < NFB; ++fb)
+        for (int j = 0; j < 4; ++j)
+            for (int l = 0; l < 64; ++l) {
+                const int f = fb * 16 + 4 * (l >> 4) + j;
+                lastf[(fb * 4 + j) * 64 + l] = tap(f, T - 1);
+                lasta[(fb * 4 + j) * 64 + l] = a2(f) * tap(f, T - 1);
+            }
+    out->m = m;
+    out->nf = nf;
+    out->nfb = NFB;
+    hipError_t e = hipMalloc((void **)&out->fwd, fwd.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&out->adj, adj.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&out->lastf, lastf.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&out->lasta, lasta.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(out->fwd, fwd.data(), fwd.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(out->adj, adj.data(), adj.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(out->lastf, lastf.data(), lastf.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(out->lasta, lasta.data(), lasta.size() * 4, hipMemcpyHostToDevice);
+    return e;
+}
+
+void fused_release(FusedBank *b)
+{
+    (void)hipFree(b->fwd);
+    (void)hipFree(b->adj);
+    (void)hipFree(b->lastf);
+    (void)hipFree(b->lasta);
+    b->fwd = b->adj = b->lastf = b->lasta = nullptr;
+}
+
+// Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
+// count is chosen to fill the chip: the smallest per-CU work over rounds of
+// 256 workgroups, each tile costing ceil((ty + 2r) / 8) pipeline steps.
+void make_plan(int m, const fe_job *jobs, int n, Plan *plan)
+{
+    const int R = (m - 1) / 2, TX = kQW - 2 * R;
+    const int kCUs = 256;
+    double best = 1e300;
+    int best_ty = 8;
+    for (int ty = 8; ty <= kMaxTileRows; ty += 1) {
+        long tiles = 0;
+        int steps = 0;
+        for (int i = 0; i < n; ++i) {
+            const int ntx = (jobs[i].width + TX - 1) / TX;
+            const int nty = (jobs[i].height + ty - 1) / ty;
+            tiles += (long)ntx * nty;
+            const int th = (jobs[i].height + nty - 1) / nty;
+            steps = std::max(steps, (th + 2 * R + kWaves - 1) / kWaves);
+        }
+        const long rounds = (tiles + kCUs - 1) / kCUs;
+        const double cost = (double)rounds * steps;
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_ty = ty;
+        }
+    }
+    plan->tile_w = TX;
+    plan->tile_h = best_ty;
+    plan->njobs = n;
+    plan->ntiles = 0;
+    plan->jobs_ntx.resize(n);
+    plan->jobs_nty.resize(n);
+    for (int i = 0; i < n; ++i) {
+        plan->jobs_ntx[i] = (jobs[i].width + TX - 1) / TX;
+        plan->jobs_nty[i] = (jobs[i].height + best_ty - 1) / best_ty;
+        plan->ntiles += plan->jobs_ntx[i] * plan->jobs_nty[i];
+    }
+}
+
+size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(JobDesc); }
+
+hipError_t run_fused(const FusedBank &bank, const Plan &plan, const fe_job *jobs, int n,
+                     float **ua, float **ub, void *plan_ws, hipStream_t s)
+{
+    JobDesc *dj = (JobDesc *)plan_ws;
+    int max_it = 0, base = 0;
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+        JobChunk ch{};
+        ch.first = c0;
+        ch.count = std::min(kChunk, n - c0);
+        for (int i = 0; i < ch.count; ++i) {
+            const fe_job &j = jobs[c0 + i];
+            JobDesc &d = ch.d[i];
+            d.counts = j.counts;
+            d.ua = ua[c0 + i];
+            d.ub = ub[c0 + i];
+            d.H = j.height;
+            d.W = j.width;
+            d.ntx = plan.jobs_ntx[c0 + i];
+            d.nty = plan.jobs_nty[c0 + i];
+            d.tile_base = base;
+            base += d.ntx * d.nty;
+            d.iters = j.iterations;
+            d.tau = j.tau;
+            d.gamma = j.gamma;
+            d.tl = j.tau * j.lambda;
+            d.data_term = j.data_term == FE_DATA_AUTO
+                              ? (j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV)
+                              : j.data_term;
+            max_it = std::max(max_it, j.iterations);
+        }
+        write_jobs_kernel<<<1, kChunk, 0, s>>>(ch, dj);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int nfb = nfb_for(bank.nf);
+    for (int it = 0; it < max_it; ++it) {
+        hipError_t e = hipErrorInvalidValue;
+#define FE_STEP(MM, NB) e = launch_step<MM, NB>(bank, dj, n, plan.ntiles, it, plan.tile_h, s)
+        switch (bank.m * 10 + nfb) {
+        case 31: FE_STEP(3, 1); break;
+        case 32: FE_STEP(3, 2); break;
+        case 33: FE_STEP(3, 3); break;
+        case 34: FE_STEP(3, 4); break;
+        case 51: FE_STEP(5, 1); break;
+        case 52: FE_STEP(5, 2); break;
+        case 53: FE_STEP(5, 3); break;
+        case 54: FE_STEP(5, 4); break;
+        case 71: FE_STEP(7, 1); break;
+        case 72: FE_STEP(7, 2); break;
+        case 73: FE_STEP(7, 3); break;
+        case 74: FE_STEP(7, 4); break;
+        default: break;
+        }
+#undef FE_STEP
+        if (e != hipSuccess) return e;
+    }
+    // the last iterate of job i is in ua when its count is even, else ub
+    for (int i = 0; i < n; ++i)
+        if (jobs[i].iterations & 1) std::swap(ua[i], ub[i]);
+    return hipSuccess;
+}
+
 }  // namespace fe
