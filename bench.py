@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--iterations", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (a "
+                         "known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the denoiser's images are independent "
@@ -95,6 +98,12 @@ def main():
         if st != 0:
             raise fe.FeError(st, lib.fe_last_error().decode())
 
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -111,7 +120,7 @@ def main():
     ms_per_step = gpu_ms / args.steps
     px_it = sum(j.height * j.width * j.iterations for j in cfg["jobs"])
     value = px_it / (ms_per_step * 1e-3) / 1e6
-    launches = sum(j.iterations for j in cfg["jobs"])
+    launches = max(j.iterations for j in cfg["jobs"])
     achieved = flops_per_px_it(m, nf) * px_it / (ms_per_step * 1e-3) / 1e12
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpixel-iter/s",

@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "fe_internal.h"
@@ -44,6 +45,11 @@ namespace fe {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Global-memory float.  Pointers read out of the job table are generic;
+// accesses through them would compile to FLAT instructions, which also
+// count against the LDS wait counter and would make every LDS wait wait for
+// HBM as well.
+typedef __attribute__((address_space(1))) float gfloat;
 
 constexpr int kWaves = 8;             // waves per workgroup
 constexpr int kThreads = 64 * kWaves; // 512
@@ -71,14 +77,14 @@ struct Geo {
     static constexpr int TX = kQW - 2 * R;            // output columns per tile
     static constexpr int UC = kQW + 2 * R;            // u tile columns
     static constexpr int US = UC + 2;                 // u tile row stride (floats)
-    static constexpr int SROWS = 16 * NTB + 1;        // scratch rows (taps; last tap last)
+    static constexpr int SROWS = (16 * NTB > T) ? 16 * NTB : T;  // scratch rows = taps
     static constexpr int SPAD = 8;                    // zero columns left of a block
     static constexpr int SW = 36;                     // scratch row stride (floats)
-    static constexpr int HR = kWaves + 2 * R;         // H ring slots (q-rows)
+    static constexpr int HR = 2 * kWaves + 2 * R;     // H ring slots (q-rows)
     static constexpr int XSPAN = 16 + 2 * R;          // columns one block reaches
     static constexpr int TASKS = M * XSPAN;           // (a, x) collapse tasks per block
     static constexpr int ROUNDS = (TASKS + 63) / 64;
-    static constexpr int LAST_ROW = 16 * NTB;         // scratch row of the last tap
+    static constexpr int LAST_ROW = T - 1;            // scratch row of the last tap
 };
 
 template <int M>
@@ -96,13 +102,20 @@ __device__ __forceinline__ int sym_clamp(int i, int n)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
-// Orders this wave's LDS writes before its later LDS reads (and vice versa)
-// across lanes: the compiler reasons per lane and could otherwise move them.
-__device__ __forceinline__ void wave_lds_sync()
+// Keeps this wave's LDS accesses in program order at compile time.  The LDS
+// executes one wave's requests in issue order, so a lane reading what
+// another lane of the same wave wrote earlier needs no wait, only that the
+// compiler (which reasons per lane) does not move the accesses.
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+// Workgroup barrier that orders LDS only.  __syncthreads() would also wait
+// for this wave's outstanding global stores (the finished output rows),
+// which nothing in the workgroup reads back during the launch.
+__device__ __forceinline__ void lds_barrier()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int M, int NFB>
@@ -138,8 +151,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int x0 = (int)((long)tix * W / J.ntx), x1 = (int)((long)(tix + 1) * W / J.ntx);
     const int y0 = (int)((long)tiy * H / J.nty), y1 = (int)((long)(tiy + 1) * H / J.nty);
     const int tx = x1 - x0, ty = y1 - y0;
-    const float *__restrict__ ucur = (iter & 1) ? J.ub : J.ua;
-    float *uprev = (iter & 1) ? J.ua : J.ub;   // u^{n-1}, overwritten by u^{n+1}
+    const gfloat *ucur = (const gfloat *)((iter & 1) ? J.ub : J.ua);
+    gfloat *uprev = (gfloat *)((iter & 1) ? J.ua : J.ub);  // u^{n-1} -> u^{n+1}
+    const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
     float *S = U + (size_t)(ty_max + 4 * R) * G::US;       // kWaves x SROWS x SW
@@ -176,6 +190,21 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         boff[s] = (t / M) * G::US + (t % M) + p;
     }
     const int loff = (M - 1) * G::US + (M - 1) + p;  // last tap
+    // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
+    // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
+    // block column xr + R; hoff: H offset of (a, xr); valid: task exists.
+    int sbase[G::ROUNDS], hoff[G::ROUNDS], xrr[G::ROUNDS];
+#pragma unroll
+    for (int rr = 0; rr < G::ROUNDS; ++rr) {
+        const int task = rr * 64 + lane;
+        const int a = task / G::XSPAN;
+        const int xr = task - a * G::XSPAN - R;
+        const bool ok = task < G::TASKS;
+        sbase[rr] = (a * M) * G::SW + G::SPAD + xr + R;
+        hoff[rr] = a * kQW + xr;
+        xrr[rr] = ok ? xr : -1000;   // never a valid column when the task is absent
+    }
+    const int perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;
 
     // ---- zero this wave's scratch (its pad columns stay zero) -------------
     for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
@@ -192,106 +221,158 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     const int nq = ty + 2 * R;                 // q-rows of the tile
     const int nsteps = (nq + kWaves - 1) / kWaves;
-    for (int st = 0; st < nsteps; ++st) {
-        // ================= q-row: forward, influence, adjoint, collapse =====
-        const int qr = st * kWaves + wave;
-        const int qy = y0 - R + qr;            // image row of this q-row
-        if (qr < nq && qy >= 0 && qy < H) {
-            float *Hs = Hr + (size_t)(qr % G::HR) * M * kQW;
-            for (int k = 0; k < kQB; ++k) {
-                const float *Ub = U + qr * G::US + 16 * k;
-                f32x4 z[NFB];
+
+    // ---- one 16-pixel block: forward bank into z (matrix cores) -----------
+    auto forward = [&](int qr, int k, f32x4 (&z)[NFB], float &ul) {
+        const float *Ub = U + qr * G::US + 16 * k;
 #pragma unroll
-                for (int fb = 0; fb < NFB; ++fb) z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int fb = 0; fb < NFB; ++fb) z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int s = 0; s < G::KF; ++s) {
-                    const float b = Ub[boff[s]];
+        for (int s = 0; s < G::KF; ++s) {
+            const float b = Ub[boff[s]];
 #pragma unroll
-                    for (int fb = 0; fb < NFB; ++fb)
-                        z[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afwd[s][fb], b, z[fb], 0, 0, 0);
-                }
-                const float ul = Ub[loff];
-                const int qx = x0 - R + 16 * k + p;
-                const bool inside = qx >= 0 && qx < W;
-                f32x4 c[G::NTB];
+            for (int fb = 0; fb < NFB; ++fb)
+                z[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afwd[s][fb], b, z[fb], 0, 0, 0);
+        }
+        ul = Ub[loff];
+    };
+    // ---- influence, adjoint bank, tap contributions into the scratch ------
+    auto adjoint_impl = [&](auto mask_tag, int k, const f32x4 (&z)[NFB], float ul) {
+        constexpr bool MASK = decltype(mask_tag)::value;
+        const int qx = x0 - R + 16 * k + p;
+        const bool inside = qx >= 0 && qx < W;
+        f32x4 c[G::NTB];
 #pragma unroll
-                for (int nb = 0; nb < G::NTB; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-                float part = 0.0f;
+        for (int nb = 0; nb < G::NTB; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float part = 0.0f;
 #pragma unroll
-                for (int fb = 0; fb < NFB; ++fb) {
+        for (int fb = 0; fb < NFB; ++fb) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float zz = fmaf(lastf[fb][j], ul, z[fb][j]);
-                        const float phi = inside ? zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f)) : 0.0f;
-#pragma unroll
-                        for (int nb = 0; nb < G::NTB; ++nb)
-                            c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
-                        part = fmaf(lasta[fb][j], phi, part);
-                    }
-                }
-                part += __shfl_xor(part, 16);
-                part += __shfl_xor(part, 32);
-                // C[px = 4g + jj][tap = 16 nb + p] -> scratch row = tap, column = px
+            for (int j = 0; j < 4; ++j) {
+                const float zz = fmaf(lastf[fb][j], ul, z[fb][j]);
+                float phi = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
+                if (MASK) phi = inside ? phi : 0.0f;
 #pragma unroll
                 for (int nb = 0; nb < G::NTB; ++nb)
-                    *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
-                if (g == 0) Sw[G::LAST_ROW * G::SW + G::SPAD + p] = part;
-                wave_lds_sync();
-                // horizontal collapse: H[a][16k + xr] (+)= sum_b C[xr + R - b][(a, b)]
-#pragma unroll
-                for (int rr = 0; rr < G::ROUNDS; ++rr) {
-                    const int task = rr * 64 + lane;
-                    if (task < G::TASKS) {
-                        const int a = task / G::XSPAN;
-                        const int xr = task - a * G::XSPAN - R;
-                        float acc = 0.0f;
-#pragma unroll
-                        for (int b = 0; b < M; ++b) {
-                            const int t = a * M + b;
-                            const int row = (t < G::T - 1) ? t : G::LAST_ROW;
-                            acc += Sw[row * G::SW + G::SPAD + xr + R - b];
-                        }
-                        const int x = 16 * k + xr;
-                        if (x >= 0 && x < kQW) {
-                            float *h = Hs + a * kQW + x;
-                            *h = (k > 0 && xr < R) ? *h + acc : acc;
-                        }
-                    }
-                }
-                wave_lds_sync();
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
+                part = fmaf(lasta[fb][j], phi, part);
             }
         }
-        __syncthreads();
-        // ================= output rows whose q-rows are all done ============
+        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm16, __float_as_int(part)));
+        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm32, __float_as_int(part)));
+        // C[px = 4g + jj][tap = 16 nb + p] -> scratch row = tap, column = px
+#pragma unroll
+        for (int nb = 0; nb < G::NTB; ++nb)
+            *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
+        if (g == 0) Sw[G::LAST_ROW * G::SW + G::SPAD + p] = part;
+    };
+    // Pixels of block k outside the image carry psi = 0 (the adjoint's
+    // input vanishes off the image); blocks wholly inside skip the mask.
+    auto adjoint = [&](int k, const f32x4 (&z)[NFB], float ul) {
+        const int q0 = x0 - R + 16 * k;
+        if (q0 >= 0 && q0 + 15 < W)
+            adjoint_impl(std::integral_constant<bool, false>{}, k, z, ul);
+        else
+            adjoint_impl(std::integral_constant<bool, true>{}, k, z, ul);
+    };
+    // ---- horizontal collapse of block k into the q-row's H slot -----------
+    //   H[a][16k + xr] (+)= sum_b C[xr + R - b][(a, b)]; the first block to
+    //   reach a column writes it, the next one adds.
+    auto collapse = [&](float *Hs, int k) {
+#pragma unroll
+        for (int rr = 0; rr < G::ROUNDS; ++rr) {
+            const int xr = xrr[rr];
+            const int x = 16 * k + xr;
+            if (x >= 0 && x < kQW) {           // false for absent tasks
+                const float *sp = Sw + sbase[rr];
+                float acc = sp[0];
+#pragma unroll
+                for (int b = 1; b < M; ++b) acc += sp[b * (G::SW - 1)];
+                float *h = Hs + hoff[rr] + 16 * k;
+                *h = (k > 0 && xr < R) ? *h + acc : acc;
+            }
+        }
+    };
+    // ---- output rows: g = sum over ghosts and a of H; iPiano update --------
+    // Inputs of the row a wave will finish are fetched one step ahead.
+    float pf_up = 0.0f, pf_y = 0.0f;
+    auto prefetch = [&](int st) {
         const int orow = st * kWaves - 2 * R + wave;
         if (orow >= 0 && orow < ty && lane < tx) {
-            const int y = y0 + orow, x = x0 + lane;
-            int rows[3], nr = 0;
-            if (y < R) rows[nr++] = -1 - y;
-            rows[nr++] = y;
-            if (y >= H - R) rows[nr++] = 2 * H - 1 - y;
-            const int hx = x - (x0 - R);
-            const int hxl = (x < R) ? (-1 - x) - (x0 - R) : -1;
-            const int hxr = (x >= W - R) ? (2 * W - 1 - x) - (x0 - R) : -1;
-            float gsum = 0.0f;
-            for (int ir = 0; ir < nr; ++ir) {
-#pragma unroll
-                for (int a = 0; a < M; ++a) {
-                    const int qyy = rows[ir] - a + R;
-                    if (qyy < 0 || qyy >= H) continue;
-                    const int q = qyy - (y0 - R);
-                    const float *h = Hr + (size_t)(q % G::HR) * M * kQW + a * kQW;
-                    if (hxl >= 0) gsum += h[hxl];
-                    gsum += h[hx];
-                    if (hxr >= 0) gsum += h[hxr];
-                }
-            }
-            const long pix = (long)y * W + x;
-            const float uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
-            const float ut = inertial_step(uc, uprev[pix], gsum, J.tau, J.gamma);
-            uprev[pix] = prox(ut, anscombe(J.counts[pix]), J.tl, J.data_term);
+            const long pix = (long)(y0 + orow) * W + x0 + lane;
+            pf_up = uprev[pix];
+            pf_y = counts[pix];
         }
-        __syncthreads();
+    };
+    auto finalize = [&](int st) {
+        const int orow = st * kWaves - 2 * R + wave;
+        if (orow < 0 || orow >= ty) return;    // uniform over the wave
+        const int y = y0 + orow;
+        const int x = x0 + (lane < tx ? lane : tx - 1);
+        // the output row and, at the top or bottom border, its ghost rows
+        int rows[3], nr = 0;
+        if (y < R) rows[nr++] = -1 - y;
+        rows[nr++] = y;
+        if (y >= H - R) rows[nr++] = 2 * H - 1 - y;
+        // the column and, at the left or right border, its ghost columns
+        // (both when W < 2R)
+        const int hx = x - (x0 - R);
+        const bool gl = x < R, gr = x >= W - R;
+        const int hgl = gl ? (-1 - x) - (x0 - R) : hx;
+        const int hgr = gr ? (2 * W - 1 - x) - (x0 - R) : hx;
+        float gsum = 0.0f;
+        for (int ir = 0; ir < nr; ++ir) {
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                const int qyy = rows[ir] - a + R;
+                if (qyy < 0 || qyy >= H) continue;     // uniform
+                int q = qyy - (y0 - R);
+                q = q >= G::HR ? q % G::HR : q;
+                const float *h = Hr + (size_t)q * M * kQW + a * kQW;
+                const float vl = h[hgl], vr = h[hgr];
+                gsum += h[hx];
+                gsum += gl ? vl : 0.0f;
+                gsum += gr ? vr : 0.0f;
+            }
+        }
+        if (lane >= tx) return;
+        const float uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
+        const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
+        uprev[(long)y * W + x] = prox(ut, anscombe(pf_y), J.tl, J.data_term);
+    };
+
+    // Step st: finish the output rows of step st - 1, then run q-row
+    // st * 8 + wave.  One barrier per step; the H ring holds 2 * 8 + 2R
+    // q-rows so the rows being finished and the rows being written never
+    // share a slot.
+    for (int st = 0; st <= nsteps; ++st) {
+        if (st > 0) finalize(st - 1);
+        if (st < nsteps) {
+            prefetch(st);
+            const int qr = st * kWaves + wave;
+            const int qy = y0 - R + qr;
+            if (qr < nq && qy >= 0 && qy < H) {
+                float *Hs = Hr + (size_t)(qr % G::HR) * M * kQW;
+                f32x4 z[NFB];
+                float ul;
+                // software pipeline: the collapse of block k - 1 (LDS, VALU)
+                // is issued next to the forward MFMAs of block k
+                forward(qr, 0, z, ul);
+                adjoint(0, z, ul);
+#pragma unroll
+                for (int k = 1; k < kQB; ++k) {
+                    lds_order();
+                    forward(qr, k, z, ul);
+                    collapse(Hs, k - 1);
+                    lds_order();
+                    adjoint(k, z, ul);
+                }
+                lds_order();
+                collapse(Hs, kQB - 1);
+                lds_order();
+            }
+        }
+        lds_barrier();
     }
 }
 
