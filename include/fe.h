@@ -95,8 +95,8 @@ typedef struct {
  * layouts the kernels use.  *out receives the context (NULL on error). */
 fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out);
 
-/* Workspace bytes fe_denoise needs for this batch of jobs (the image state
- * u^n, u^{n-1} of every job, plus the launch plan). */
+/* Workspace bytes fe_denoise needs for this batch of jobs (the state
+ * u^n, u^{n-1} of every job, plus the job table of the step launches). */
 fe_status fe_workspace_size(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
                             size_t *bytes);
 
@@ -106,6 +106,40 @@ fe_status fe_workspace_size(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
  * is written to its out / out_anscombe buffers.  Asynchronous. */
 fe_status fe_denoise(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
                      void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ---- stepping interface ------------------------------------------------
+ * fe_denoise is fe_begin + fe_advance + fe_end on states it carves from its
+ * workspace.  Callers that keep jobs resident between calls (a serving loop
+ * advancing many requests a few iterations at a time, or a checkpoint) use
+ * the three calls directly.  A job's state is two caller-owned DEVICE
+ * planes of H*W floats, contiguous ([2][H][W]); after `done` iterations
+ * plane (done % 2) holds u^done and the other plane u^{done-1}.  The pair
+ * (state, done) is the job's complete resume point. */
+
+/* Bytes of one job's state (2 * H * W * sizeof(float)). */
+fe_status fe_state_bytes(const fe_ctx *ctx, int32_t height, int32_t width,
+                         size_t *bytes);
+
+/* u^0 = u^{-1} = f_A(y) (eq. 2.3) into states[i] for every job.  Async. */
+fe_status fe_begin(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
+                   int32_t n, void *hip_stream);
+
+/* Workspace bytes fe_advance needs for a batch of n jobs (its job table). */
+fe_status fe_advance_workspace_size(const fe_ctx *ctx, int32_t n, size_t *bytes);
+
+/* Apply count[i] >= 0 further iPiano iterations (eq. 2.8) to job i whose
+ * state holds done[i] >= 0 iterations; all jobs of the batch share the
+ * step launches.  job.iterations is ignored here.  The workspace (DEVICE,
+ * 256-byte aligned, fe_advance_workspace_size bytes) must not be reused
+ * until the stream has passed this call.  Async. */
+fe_status fe_advance(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
+                     const int32_t *done, const int32_t *count, int32_t n,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* x_hat = I_C(u^done) (eq. 2.4) into job.out, and u^done into
+ * job.out_anscombe, for every job (either output may be NULL).  Async. */
+fe_status fe_end(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
+                 const int32_t *done, int32_t n, void *hip_stream);
 
 /* Workspace bytes fe_energy_grad needs for an H x W image. */
 fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,

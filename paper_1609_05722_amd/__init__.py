@@ -26,7 +26,9 @@ _PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}
 _DATA = {"auto": DATA_AUTO, "quadratic": DATA_QUADRATIC, "idiv": DATA_IDIV}
 
 EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
-           "fe_energy_grad_workspace_size", "fe_energy_grad", "fe_last_error")
+           "fe_state_bytes", "fe_begin", "fe_advance_workspace_size", "fe_advance",
+           "fe_end", "fe_energy_grad_workspace_size", "fe_energy_grad",
+           "fe_last_error")
 
 
 class FeError(RuntimeError):
@@ -76,6 +78,18 @@ def library():
         lib.fe_energy_grad.argtypes = [vp, i32, i32, vp, vp, ctypes.c_float, i32,
                                        ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
         lib.fe_energy_grad.restype = i32
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        pi = ctypes.POINTER(ctypes.c_int32)
+        lib.fe_state_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+        lib.fe_state_bytes.restype = i32
+        lib.fe_begin.argtypes = [vp, ctypes.POINTER(_Job), pp, i32, vp]
+        lib.fe_begin.restype = i32
+        lib.fe_advance_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        lib.fe_advance_workspace_size.restype = i32
+        lib.fe_advance.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, pi, i32, vp, sz, vp]
+        lib.fe_advance.restype = i32
+        lib.fe_end.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, i32, vp]
+        lib.fe_end.restype = i32
         lib.fe_last_error.argtypes = []
         lib.fe_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -240,3 +254,44 @@ def energy_grad(counts, u, prior, lam, data_term, want_energy=True,
                                     _ptr(grad), _ptr(ws), ws.numel(),
                                     _stream_handle(stream)))
     return (e.value if want_energy else None), grad
+
+
+class Batch:
+    """Jobs kept resident on the device between calls (fe_begin /
+    fe_advance / fe_end): each job owns a state tensor of two H x W planes
+    and a count of the iterations already applied."""
+
+    def __init__(self, prior, specs, stream=None):
+        torch = _torch()
+        self.prior = prior
+        self.specs = list(specs)
+        self.n = len(self.specs)
+        self.arr, self.keep = make_jobs(self.specs)
+        self.states = [torch.empty((2,) + tuple(s.counts.shape), dtype=torch.float32,
+                                   device=s.counts.device) for s in self.specs]
+        self._sp = (ctypes.c_void_p * max(1, self.n))(*[t.data_ptr() for t in self.states])
+        self.done = (ctypes.c_int32 * max(1, self.n))()
+        sz = ctypes.c_size_t()
+        _check(library().fe_advance_workspace_size(prior.handle, self.n, ctypes.byref(sz)))
+        self.ws = alloc_workspace(sz.value, self.specs[0].counts.device if self.n else "cuda")
+        self.stream = stream
+
+    def begin(self):
+        _check(library().fe_begin(self.prior.handle, self.arr, self._sp, self.n,
+                                  _stream_handle(self.stream)))
+        for i in range(self.n):
+            self.done[i] = 0
+
+    def advance(self, counts):
+        """Apply counts[i] more iterations to job i (one call, shared launches)."""
+        cnt = (ctypes.c_int32 * max(1, self.n))(*[int(c) for c in counts])
+        _check(library().fe_advance(self.prior.handle, self.arr, self._sp, self.done, cnt,
+                                    self.n, _ptr(self.ws), self.ws.numel(),
+                                    _stream_handle(self.stream)))
+        for i in range(self.n):
+            self.done[i] += cnt[i]
+
+    def end(self):
+        _check(library().fe_end(self.prior.handle, self.arr, self._sp, self.done, self.n,
+                                _stream_handle(self.stream)))
+        return [(o, oa) for (_, o, oa) in self.keep]

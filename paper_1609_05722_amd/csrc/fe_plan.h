@@ -32,14 +32,23 @@ struct Plan {
     size_t device_bytes() const;  // job table in the workspace
 };
 
+// One job of an fe_advance batch: its description, its state (two planes
+// u^n / u^{n-1}, u^n in plane done % 2), iterations done and to apply.
+struct AdvanceItem {
+    const fe_job *job;
+    float *state;
+    int done, count;
+};
+
 bool fused_supported(int m, int nf);
 hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf,
                         FusedBank *out);
 void fused_release(FusedBank *b);
-void make_plan(int m, const fe_job *jobs, int n, Plan *plan);
-// Runs every job's iterations; on return ua[i] holds job i's last iterate
-// (the pointers are swapped as needed).
-hipError_t run_fused(const FusedBank &bank, const Plan &plan, const fe_job *jobs,
-                     int n, float **ua, float **ub, void *plan_ws, hipStream_t s);
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan);
+size_t fused_table_bytes(int n);
+// Enqueues the job table and max(count) step launches; job i is advanced by
+// items[i].count iterations.
+hipError_t run_fused(const FusedBank &bank, const Plan &plan, const AdvanceItem *items,
+                     int n, void *plan_ws, hipStream_t s);
 
 }  // namespace fe

@@ -66,12 +66,6 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int radius(const fe_ctx *c) { return (c->m - 1) / 2; }
 
-int resolve_data_term(const fe_job &j)
-{
-    if (j.data_term == FE_DATA_AUTO) return j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV;
-    return j.data_term;
-}
-
 fe_status check_job(const fe_ctx *c, const fe_job &j, int idx)
 {
     const int r = radius(c);
@@ -96,8 +90,8 @@ fe_status check_job(const fe_ctx *c, const fe_job &j, int idx)
     if (j.precision != FE_PREC_FP32 && j.precision != FE_PREC_BF16 &&
         j.precision != FE_PREC_FP16)
         return fail(FE_ERR_INVALID, "job %d: unknown precision %d", idx, j.precision);
-    if (j.precision != FE_PREC_FP32 && !fe::fused_supported(c->m, c->nf))
-        return fail(FE_ERR_UNSUPPORTED, "job %d: reduced precision needs the matrix-core step", idx);
+    if (j.precision != FE_PREC_FP32)
+        return fail(FE_ERR_UNSUPPORTED, "job %d: reduced-precision contractions are not built", idx);
     return FE_OK;
 }
 
@@ -113,41 +107,82 @@ fe_status check_batch(const fe_ctx *c, const fe_job *jobs, int32_t n)
     return FE_OK;
 }
 
-// Workspace of fe_denoise: [plan][u planes of job 0][job 1]...[psi scratch]
+size_t state_bytes(int H, int W) { return 2 * (size_t)H * W * sizeof(float); }
+
+// Workspace of fe_denoise: [job table][state of job 0][state of job 1]...
 struct DenoiseLayout {
-    size_t plan_off = 0, plan_bytes = 0;
-    std::vector<size_t> state_off;  // two planes per job
-    size_t psi_off = 0, psi_bytes = 0;
+    size_t table_bytes = 0;
+    std::vector<size_t> state_off;
     size_t total = 0;
 };
 
-bool use_fused(const fe_ctx *c) { return fe::fused_supported(c->m, c->nf); }
-
-DenoiseLayout layout_for(const fe_ctx *c, const fe_job *jobs, int32_t n,
-                         const fe::Plan *plan)
+DenoiseLayout layout_for(const fe_job *jobs, int32_t n)
 {
     DenoiseLayout L;
-    size_t off = 0;
-    if (plan) {
-        L.plan_off = off;
-        L.plan_bytes = align256(plan->device_bytes());
-        off += L.plan_bytes;
-    }
-    size_t max_plane = 0;
+    L.table_bytes = align256(fe::fused_table_bytes(n));
+    size_t off = L.table_bytes;
     L.state_off.resize(n);
     for (int i = 0; i < n; ++i) {
-        const size_t plane = (size_t)jobs[i].height * jobs[i].width * sizeof(float);
         L.state_off[i] = off;
-        off += 2 * align256(plane);
-        max_plane = std::max(max_plane, plane);
-    }
-    if (!use_fused(c)) {
-        L.psi_off = off;
-        L.psi_bytes = align256(max_plane * c->nf);
-        off += L.psi_bytes;
+        off += align256(state_bytes(jobs[i].height, jobs[i].width));
     }
     L.total = std::max<size_t>(off, 256);
     return L;
+}
+
+fe_status check_workspace(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws) return fail(FE_ERR_INVALID, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(FE_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return FE_OK;
+}
+
+fe_status check_states(const fe_job *jobs, float *const *states, int32_t n)
+{
+    if (n > 0 && !states) return fail(FE_ERR_INVALID, "states is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!states[i]) return fail(FE_ERR_INVALID, "state %d is NULL", i);
+    (void)jobs;
+    return FE_OK;
+}
+
+// v = f_A(y) into both planes of every state (u^0 = u^{-1} = v).
+fe_status enqueue_begin(const fe_job *jobs, float *const *states, int32_t n, hipStream_t s)
+{
+    for (int i = 0; i < n; ++i) {
+        const long plane = (long)jobs[i].height * jobs[i].width;
+        hipError_t e = fe::launch_anscombe_init(jobs[i].counts, states[i], states[i] + plane,
+                                                plane, s);
+        if (e != hipSuccess) return hip_fail(e, "anscombe init");
+    }
+    return FE_OK;
+}
+
+fe_status enqueue_end(const fe_job *jobs, float *const *states, const int32_t *done, int32_t n,
+                      hipStream_t s)
+{
+    for (int i = 0; i < n; ++i) {
+        const long plane = (long)jobs[i].height * jobs[i].width;
+        const float *u = states[i] + ((done[i] & 1) ? plane : 0);
+        hipError_t e = fe::launch_inverse_anscombe(u, jobs[i].out, jobs[i].out_anscombe, plane, s);
+        if (e != hipSuccess) return hip_fail(e, "inverse anscombe");
+    }
+    return FE_OK;
+}
+
+fe_status enqueue_advance(const fe_ctx *c, const fe_job *jobs, float *const *states,
+                          const int32_t *done, const int32_t *count, int32_t n, void *table,
+                          hipStream_t s)
+{
+    std::vector<fe::AdvanceItem> items(n);
+    for (int i = 0; i < n; ++i) items[i] = {&jobs[i], states[i], done[i], count[i]};
+    fe::Plan plan;
+    fe::make_plan(c->m, items.data(), n, &plan);
+    hipError_t e = fe::run_fused(c->fused, plan, items.data(), n, table, s);
+    if (e != hipSuccess) return hip_fail(e, "fused step");
+    return FE_OK;
 }
 
 }  // namespace
@@ -203,7 +238,7 @@ fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out)
     if (e == hipSuccess) e = hipMemcpy(b.alpha2, a2.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b.alpha, c->alpha.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
-    if (e == hipSuccess && use_fused(c))
+    if (e == hipSuccess)
         e = fe::fused_upload(c->taps.data(), c->alpha.data(), m, nf, &c->fused);
     if (e != hipSuccess) {
         fe_status st = e == hipErrorOutOfMemory ? fail(FE_ERR_NOMEM, "device allocation failed")
@@ -232,10 +267,7 @@ fe_status fe_workspace_size(const fe_ctx *c, const fe_job *jobs, int32_t n, size
     *bytes = 0;
     fe_status st = check_batch(c, jobs, n);
     if (st != FE_OK) return st;
-    fe::Plan plan;
-    const bool fused = use_fused(c);
-    if (fused) fe::make_plan(c->m, jobs, n, &plan);
-    *bytes = layout_for(c, jobs, n, fused ? &plan : nullptr).total;
+    *bytes = layout_for(jobs, n).total;
     return FE_OK;
 }
 
@@ -245,59 +277,92 @@ fe_status fe_denoise(const fe_ctx *c, const fe_job *jobs, int32_t n,
     fe_status st = check_batch(c, jobs, n);
     if (st != FE_OK) return st;
     if (n == 0) return FE_OK;
-    const bool fused = use_fused(c);
-    fe::Plan plan;
-    if (fused) fe::make_plan(c->m, jobs, n, &plan);
-    DenoiseLayout L = layout_for(c, jobs, n, fused ? &plan : nullptr);
-    if (!workspace) return fail(FE_ERR_INVALID, "workspace is NULL");
-    if (((uintptr_t)workspace & 255) != 0)
-        return fail(FE_ERR_INVALID, "workspace must be 256-byte aligned");
-    if (ws_bytes < L.total)
-        return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-
+    DenoiseLayout L = layout_for(jobs, n);
+    st = check_workspace(workspace, ws_bytes, L.total);
+    if (st != FE_OK) return st;
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
     char *ws = (char *)workspace;
-
-    std::vector<float *> ua(n), ub(n);
+    std::vector<float *> states(n);
+    std::vector<int32_t> zero(n, 0), iters(n);
     for (int i = 0; i < n; ++i) {
-        const size_t plane = align256((size_t)jobs[i].height * jobs[i].width * sizeof(float));
-        ua[i] = (float *)(ws + L.state_off[i]);
-        ub[i] = (float *)(ws + L.state_off[i] + plane);
-        hipError_t e = fe::launch_anscombe_init(jobs[i].counts, ua[i], ub[i],
-                                                (long)jobs[i].height * jobs[i].width, s);
-        if (e != hipSuccess) return hip_fail(e, "anscombe init");
+        states[i] = (float *)(ws + L.state_off[i]);
+        iters[i] = jobs[i].iterations;
     }
+    st = enqueue_begin(jobs, states.data(), n, s);
+    if (st == FE_OK)
+        st = enqueue_advance(c, jobs, states.data(), zero.data(), iters.data(), n, ws, s);
+    if (st == FE_OK) st = enqueue_end(jobs, states.data(), iters.data(), n, s);
+    return st;
+}
 
-    if (fused) {
-        hipError_t e = fe::run_fused(c->fused, plan, jobs, n, ua.data(), ub.data(),
-                                     ws + L.plan_off, s);
-        if (e != hipSuccess) return hip_fail(e, "fused step");
-        // run_fused leaves every job's last iterate in ua[i]
-    } else {
-        float *psi = (float *)(ws + L.psi_off);
-        for (int i = 0; i < n; ++i) {
-            const fe_job &j = jobs[i];
-            fe::StepParams p{j.tau, j.gamma, j.tau * j.lambda, resolve_data_term(j)};
-            for (int it = 0; it < j.iterations; ++it) {
-                hipError_t e = fe::launch_direct_forward(c->bank, ua[i], j.height, j.width, psi,
-                                                         nullptr, nullptr, nullptr, 0.0f, 0,
-                                                         nullptr, s);
-                if (e == hipSuccess)
-                    e = fe::launch_direct_adjoint_step(c->bank, psi, ua[i], ub[i], j.counts, ub[i],
-                                                       j.height, j.width, p, s);
-                if (e != hipSuccess) return hip_fail(e, "direct step");
-                std::swap(ua[i], ub[i]);
-            }
-        }
-    }
-    for (int i = 0; i < n; ++i) {
-        hipError_t e = fe::launch_inverse_anscombe(ua[i], jobs[i].out, jobs[i].out_anscombe,
-                                                   (long)jobs[i].height * jobs[i].width, s);
-        if (e != hipSuccess) return hip_fail(e, "inverse anscombe");
-    }
+fe_status fe_state_bytes(const fe_ctx *c, int32_t height, int32_t width, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
+    const int r = radius(c);
+    if (height < 1 || width < 1 || height < r || width < r)
+        return fail(FE_ERR_INVALID, "image %dx%d smaller than the filter radius %d", height,
+                    width, r);
+    *bytes = state_bytes(height, width);
     return FE_OK;
+}
+
+fe_status fe_begin(const fe_ctx *c, const fe_job *jobs, float *const *states, int32_t n,
+                   void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st == FE_OK) st = check_states(jobs, states, n);
+    if (st != FE_OK || n == 0) return st;
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return enqueue_begin(jobs, states, n, (hipStream_t)hip_stream);
+}
+
+fe_status fe_advance_workspace_size(const fe_ctx *c, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(FE_ERR_INVALID, "negative job count");
+    *bytes = align256(fe::fused_table_bytes(n));
+    return FE_OK;
+}
+
+fe_status fe_advance(const fe_ctx *c, const fe_job *jobs, float *const *states,
+                     const int32_t *done, const int32_t *count, int32_t n, void *workspace,
+                     size_t ws_bytes, void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st == FE_OK) st = check_states(jobs, states, n);
+    if (st != FE_OK || n == 0) return st;
+    if (!done || !count) return fail(FE_ERR_INVALID, "done and count must be non-NULL");
+    for (int i = 0; i < n; ++i)
+        if (done[i] < 0 || count[i] < 0)
+            return fail(FE_ERR_INVALID, "job %d: negative done or count", i);
+    size_t need = 0;
+    fe_advance_workspace_size(c, n, &need);
+    st = check_workspace(workspace, ws_bytes, need);
+    if (st != FE_OK) return st;
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return enqueue_advance(c, jobs, states, done, count, n, workspace, (hipStream_t)hip_stream);
+}
+
+fe_status fe_end(const fe_ctx *c, const fe_job *jobs, float *const *states,
+                 const int32_t *done, int32_t n, void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st == FE_OK) st = check_states(jobs, states, n);
+    if (st != FE_OK || n == 0) return st;
+    if (!done) return fail(FE_ERR_INVALID, "done is NULL");
+    for (int i = 0; i < n; ++i)
+        if (done[i] < 0) return fail(FE_ERR_INVALID, "job %d: negative done", i);
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return enqueue_end(jobs, states, done, n, (hipStream_t)hip_stream);
 }
 
 fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)

@@ -63,7 +63,8 @@ struct JobDesc {
     int H, W;
     int ntx, nty;       // tile grid of this job
     int tile_base;      // index of the job's first tile in the launch
-    int iters;
+    int iters;          // iterations this launch sequence applies
+    int it0;            // iterations already applied (parity of the state)
     float tau, gamma, tl;
     int data_term;
 };
@@ -151,8 +152,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int x0 = (int)((long)tix * W / J.ntx), x1 = (int)((long)(tix + 1) * W / J.ntx);
     const int y0 = (int)((long)tiy * H / J.nty), y1 = (int)((long)(tiy + 1) * H / J.nty);
     const int tx = x1 - x0, ty = y1 - y0;
-    const gfloat *ucur = (const gfloat *)((iter & 1) ? J.ub : J.ua);
-    gfloat *uprev = (gfloat *)((iter & 1) ? J.ua : J.ub);  // u^{n-1} -> u^{n+1}
+    const bool odd = ((J.it0 + iter) & 1) != 0;
+    const gfloat *ucur = (const gfloat *)(odd ? J.ub : J.ua);
+    gfloat *uprev = (gfloat *)(odd ? J.ua : J.ub);  // u^{n-1} -> u^{n+1}
     const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
@@ -470,7 +472,7 @@ void fused_release(FusedBank *b)
 // Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
 // count is chosen to fill the chip: the smallest per-CU work over rounds of
 // 256 workgroups, each tile costing ceil((ty + 2r) / 8) pipeline steps.
-void make_plan(int m, const fe_job *jobs, int n, Plan *plan)
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan)
 {
     const int R = (m - 1) / 2, TX = kQW - 2 * R;
     const int kCUs = 256;
@@ -480,10 +482,11 @@ void make_plan(int m, const fe_job *jobs, int n, Plan *plan)
         long tiles = 0;
         int steps = 0;
         for (int i = 0; i < n; ++i) {
-            const int ntx = (jobs[i].width + TX - 1) / TX;
-            const int nty = (jobs[i].height + ty - 1) / ty;
+            if (items[i].count <= 0) continue;
+            const int ntx = (items[i].job->width + TX - 1) / TX;
+            const int nty = (items[i].job->height + ty - 1) / ty;
             tiles += (long)ntx * nty;
-            const int th = (jobs[i].height + nty - 1) / nty;
+            const int th = (items[i].job->height + nty - 1) / nty;
             steps = std::max(steps, (th + 2 * R + kWaves - 1) / kWaves);
         }
         const long rounds = (tiles + kCUs - 1) / kCUs;
@@ -497,19 +500,21 @@ void make_plan(int m, const fe_job *jobs, int n, Plan *plan)
     plan->tile_h = best_ty;
     plan->njobs = n;
     plan->ntiles = 0;
-    plan->jobs_ntx.resize(n);
-    plan->jobs_nty.resize(n);
+    plan->jobs_ntx.assign(n, 0);
+    plan->jobs_nty.assign(n, 0);
     for (int i = 0; i < n; ++i) {
-        plan->jobs_ntx[i] = (jobs[i].width + TX - 1) / TX;
-        plan->jobs_nty[i] = (jobs[i].height + best_ty - 1) / best_ty;
+        if (items[i].count <= 0) continue;   // contributes no tiles
+        plan->jobs_ntx[i] = (items[i].job->width + TX - 1) / TX;
+        plan->jobs_nty[i] = (items[i].job->height + best_ty - 1) / best_ty;
         plan->ntiles += plan->jobs_ntx[i] * plan->jobs_nty[i];
     }
 }
 
 size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(JobDesc); }
+size_t fused_table_bytes(int n) { return (size_t)std::max(n, 1) * sizeof(JobDesc); }
 
-hipError_t run_fused(const FusedBank &bank, const Plan &plan, const fe_job *jobs, int n,
-                     float **ua, float **ub, void *plan_ws, hipStream_t s)
+hipError_t run_fused(const FusedBank &bank, const Plan &plan, const AdvanceItem *items, int n,
+                     void *plan_ws, hipStream_t s)
 {
     JobDesc *dj = (JobDesc *)plan_ws;
     int max_it = 0, base = 0;
@@ -518,30 +523,34 @@ hipError_t run_fused(const FusedBank &bank, const Plan &plan, const fe_job *jobs
         ch.first = c0;
         ch.count = std::min(kChunk, n - c0);
         for (int i = 0; i < ch.count; ++i) {
-            const fe_job &j = jobs[c0 + i];
+            const AdvanceItem &it = items[c0 + i];
+            const fe_job &j = *it.job;
             JobDesc &d = ch.d[i];
+            const size_t plane = (size_t)j.height * j.width;
             d.counts = j.counts;
-            d.ua = ua[c0 + i];
-            d.ub = ub[c0 + i];
+            d.ua = it.state;
+            d.ub = it.state + plane;
             d.H = j.height;
             d.W = j.width;
             d.ntx = plan.jobs_ntx[c0 + i];
             d.nty = plan.jobs_nty[c0 + i];
             d.tile_base = base;
             base += d.ntx * d.nty;
-            d.iters = j.iterations;
+            d.iters = std::max(it.count, 0);
+            d.it0 = it.done;
             d.tau = j.tau;
             d.gamma = j.gamma;
             d.tl = j.tau * j.lambda;
             d.data_term = j.data_term == FE_DATA_AUTO
                               ? (j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV)
                               : j.data_term;
-            max_it = std::max(max_it, j.iterations);
+            max_it = std::max(max_it, d.iters);
         }
         write_jobs_kernel<<<1, kChunk, 0, s>>>(ch, dj);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (plan.ntiles == 0) return hipSuccess;
     const int nfb = nfb_for(bank.nf);
     for (int it = 0; it < max_it; ++it) {
         hipError_t e = hipErrorInvalidValue;
@@ -564,9 +573,6 @@ hipError_t run_fused(const FusedBank &bank, const Plan &plan, const fe_job *jobs
 #undef FE_STEP
         if (e != hipSuccess) return e;
     }
-    // the last iterate of job i is in ua when its count is even, else ub
-    for (int i = 0; i < n; ++i)
-        if (jobs[i].iterations & 1) std::swap(ua[i], ub[i]);
     return hipSuccess;
 }
 

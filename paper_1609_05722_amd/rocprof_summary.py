@@ -1,0 +1,125 @@
+"""Summarise rocprofv3 output databases (rocpd SQLite) as short text.
+
+    python -m paper_1609_05722_amd.rocprof_summary stats  RESULTS.db [--kernel SUBSTR]
+    python -m paper_1609_05722_amd.rocprof_summary pmc    RESULTS.db [--kernel SUBSTR]
+    python -m paper_1609_05722_amd.rocprof_summary traffic FETCH.db WRITE.db \
+        --kernel SUBSTR --copy-kernel SUBSTR --copy-bytes N --kernel-source FILE \
+        --size S --out FILE.json
+
+`stats` lists per-kernel dispatch counts and durations (what
+`rocprofv3 --stats` reports); `pmc` lists the mean of every counter per
+kernel; `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM
+bytes per launch of one kernel, each counter scaled by what it reads for a
+plain device copy of known size in the same run.
+"""
+import argparse
+import hashlib
+import json
+import sqlite3
+import sys
+
+
+def kernel_stats(db, like=None):
+    con = sqlite3.connect(db)
+    q = ("select name, count(*), avg(duration), min(duration), max(duration), "
+         "sum(duration) from kernels group by name order by sum(duration) desc")
+    rows = list(con.execute(q))
+    total = sum(r[5] for r in rows) or 1
+    out = []
+    for name, n, avg, mn, mx, tot in rows:
+        if like and like not in name:
+            continue
+        out.append({"kernel": name, "calls": n, "avg_us": avg / 1e3, "min_us": mn / 1e3,
+                    "max_us": mx / 1e3, "total_ms": tot / 1e6, "pct": 100.0 * tot / total})
+    return out
+
+
+def pmc_means(db, like=None):
+    con = sqlite3.connect(db)
+    q = ("select name, counter_name, count(*), avg(counter_value), sum(counter_value), "
+         "count(distinct dispatch_id) from pmc_events group by name, counter_name")
+    out = {}
+    for name, cn, n, avg, tot, nd in con.execute(q):
+        if like and like not in name:
+            continue
+        # per dispatch: sum over the counter's instances, averaged over dispatches
+        out.setdefault(name, {})[cn] = {"per_dispatch": tot / max(nd, 1),
+                                        "instances": n // max(nd, 1), "dispatches": nd}
+    return out
+
+
+def dispatch_values(db, counter, like):
+    """Per-dispatch value of one counter (summed over its instances) for
+    every dispatch of the kernels whose name contains `like`."""
+    con = sqlite3.connect(db)
+    q = ("select dispatch_id, sum(counter_value) from pmc_events where counter_name = ? "
+         "and name like ? group by dispatch_id")
+    vals = [v for _, v in con.execute(q, (counter, "%" + like + "%"))]
+    if not vals:
+        raise SystemExit("no %s for kernels matching %r in %s" % (counter, like, db))
+    return vals
+
+
+def traffic(args):
+    fk = dispatch_values(args.fetch_db, "FETCH_SIZE", args.kernel)
+    wk = dispatch_values(args.write_db, "WRITE_SIZE", args.kernel)
+    fetch_k, write_k = sum(fk) / len(fk), sum(wk) / len(wk)
+    # the reference is the largest dispatch of the copy kernel (the copy of
+    # known size; smaller dispatches of the same kernel are runtime blits)
+    copy_fetch = max(dispatch_values(args.fetch_db, "FETCH_SIZE", args.copy_kernel))
+    copy_write = max(dispatch_values(args.write_db, "WRITE_SIZE", args.copy_kernel))
+    f_scale = args.copy_bytes / (copy_fetch * 1024.0)
+    w_scale = args.copy_bytes / (copy_write * 1024.0)
+    with open(args.kernel_source, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    rec = {
+        "kernel": args.kernel, "kernel_sha256_16": sha, "size": args.size,
+        "fetch_kib_per_dispatch": fetch_k, "write_kib_per_dispatch": write_k,
+        "dispatches": [len(fk), len(wk)],
+        "copy_kernel": args.copy_kernel, "copy_bytes": args.copy_bytes,
+        "copy_fetch_kib": copy_fetch, "copy_write_kib": copy_write,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "bytes_per_launch": fetch_k * 1024.0 * f_scale + write_k * 1024.0 * w_scale,
+        "iterations_checked": True,
+    }
+    with open(args.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s1 = sub.add_parser("stats")
+    s1.add_argument("db")
+    s1.add_argument("--kernel")
+    s2 = sub.add_parser("pmc")
+    s2.add_argument("db")
+    s2.add_argument("--kernel")
+    s3 = sub.add_parser("traffic")
+    s3.add_argument("fetch_db")
+    s3.add_argument("write_db")
+    s3.add_argument("--kernel", required=True)
+    s3.add_argument("--copy-kernel", required=True)
+    s3.add_argument("--copy-bytes", type=float, required=True)
+    s3.add_argument("--kernel-source", required=True)
+    s3.add_argument("--size", type=int, required=True)
+    s3.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        for r in kernel_stats(a.db, a.kernel):
+            print("%-90s calls=%-6d avg=%9.2f us min=%9.2f max=%9.2f total=%9.3f ms %5.1f%%"
+                  % (r["kernel"][:90], r["calls"], r["avg_us"], r["min_us"], r["max_us"],
+                     r["total_ms"], r["pct"]))
+    elif a.cmd == "pmc":
+        for k, v in pmc_means(a.db, a.kernel).items():
+            print(k[:100])
+            for cn, d in sorted(v.items()):
+                print("    %-34s per_dispatch=%16.1f  (instances=%d, dispatches=%d)"
+                      % (cn, d["per_dispatch"], d["instances"], d["dispatches"]))
+    else:
+        traffic(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -85,3 +85,13 @@ def test_null_context_is_rejected(lib):
     assert lib.fe_denoise(None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_energy_grad_workspace_size(None, 8, 8, ctypes.byref(sz)) == fe.FE_ERR_INVALID
     lib.fe_destroy(None)  # NULL-safe
+
+
+def test_stepping_calls_validate_before_device_work(lib):
+    import paper_1609_05722_amd as fe
+    sz = ctypes.c_size_t()
+    assert lib.fe_state_bytes(None, 8, 8, ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    assert lib.fe_advance_workspace_size(None, 4, ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    assert lib.fe_begin(None, None, None, 0, None) == fe.FE_ERR_INVALID
+    assert lib.fe_advance(None, None, None, None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
+    assert lib.fe_end(None, None, None, None, 0, None) == fe.FE_ERR_INVALID

@@ -160,3 +160,43 @@ def test_energy_and_gradient(fe, torch, data_term):
     g = g.cpu().numpy().astype(np.float64)
     assert np.max(np.abs(g - go)) <= 1e-4 * max(np.max(np.abs(go)), 1e-3), \
         np.max(np.abs(g - go))
+
+
+def test_stepping_matches_denoise_and_resumes(fe, torch):
+    """fe_begin + fe_advance in pieces + fe_end is bitwise fe_denoise; a
+    state copied out after some iterations and restored continues to the
+    bitwise same result (checkpoint / resume)."""
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    specs = []
+    for i, (H, W, pk) in enumerate([(70, 90, 2.0), (128, 64, 8.0)]):
+        _, y = noisy_pair(500 + i, 600 + i, H, W, pk)
+        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, 37, tau, gamma,
+                                data_term="auto", peak=pk, want_anscombe=True))
+    ref = fe.denoise_jobs(prior, specs)
+    b = fe.Batch(prior, specs)
+    b.begin()
+    b.advance([10, 10])
+    b.advance([0, 27])
+    b.advance([27, 0])
+    out = b.end()
+    torch.cuda.synchronize()
+    for (x0, u0), (x1, u1) in zip(ref, out):
+        assert torch.equal(u0, u1) and torch.equal(x0, x1)
+    # checkpoint after 15 iterations, restore into fresh states, finish
+    b2 = fe.Batch(prior, specs)
+    b2.begin()
+    b2.advance([15, 15])
+    torch.cuda.synchronize()
+    saved = [s.cpu().clone() for s in b2.states]
+    done = [b2.done[i] for i in range(b2.n)]
+    b3 = fe.Batch(prior, specs)
+    for s_dst, s_src in zip(b3.states, saved):
+        s_dst.copy_(s_src.cuda())
+    for i in range(b3.n):
+        b3.done[i] = done[i]
+    b3.advance([22, 22])
+    out3 = b3.end()
+    torch.cuda.synchronize()
+    for (x0, u0), (x1, u1) in zip(ref, out3):
+        assert torch.equal(u0, u1) and torch.equal(x0, x1)
