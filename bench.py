@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FoE step Mpixel-iter/s vs roofline; served images/s + p50/p99 latency"
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 (matrix)
 HBM_PEAK_GBS = 8000.0
+MFMA16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 / fp16 matrix
 
 
 def flops_per_px_it(m, nf):
@@ -87,6 +88,8 @@ def main():
     ap.add_argument("--iterations", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the bf16 / fp16 contraction timings")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a "
                          "known-size reference for HBM byte counters)")
@@ -106,22 +109,54 @@ def main():
     k, a = prior_for(m, nf)
     tau, gamma = step_size_for(m, nf)
     prior = fe.Prior(k, a, device=0)
-    specs = []
-    for j in cfg["jobs"]:
-        _, y = j.arrays()
-        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), j.lam, j.iterations, tau,
-                                gamma, data_term=j.data_term, peak=j.peak))
-    arr, keep = fe.make_jobs(specs)
-    n = len(specs)
-    ws = fe.alloc_workspace(fe.workspace_size(prior, arr, n), "cuda")
+    counts = [torch.from_numpy(j.arrays()[1]).cuda() for j in cfg["jobs"]]
     stream = torch.cuda.current_stream()
     lib = fe.library()
+    its = max(j.iterations for j in cfg["jobs"])
+    px_it = sum(j.height * j.width * j.iterations for j in cfg["jobs"])
+    px_per_launch = sum(j.height * j.width for j in cfg["jobs"])
 
-    def step():
-        st = lib.fe_denoise(prior.handle, arr, n, fe._ptr(ws), ws.numel(),
-                            fe._stream_handle(stream))
-        if st != 0:
-            raise fe.FeError(st, lib.fe_last_error().decode())
+    def measure(precision, steps, warmup):
+        specs = [fe.JobSpec(c, j.lam, j.iterations, tau, gamma, data_term=j.data_term,
+                            peak=j.peak, precision=precision)
+                 for c, j in zip(counts, cfg["jobs"])]
+        arr, keep = fe.make_jobs(specs)
+        n = len(specs)
+        ws = fe.alloc_workspace(fe.workspace_size(prior, arr, n), "cuda")
+
+        def step():
+            st = lib.fe_denoise(prior.handle, arr, n, fe._ptr(ws), ws.numel(),
+                                fe._stream_handle(stream))
+            if st != 0:
+                raise fe.FeError(st, lib.fe_last_error().decode())
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_per_step = ev0.elapsed_time(ev1) / steps
+        # The dominant kernel: the fused step launches of one fe_advance call
+        # (same jobs, same plan), timed with HIP events on the same stream.
+        batch = fe.Batch(prior, specs, stream=stream)
+        kern_ms = []
+        for _ in range(max(1, steps)):
+            batch.begin()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.advance([j.iterations for j in cfg["jobs"]])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kern_ms.append(e0.elapsed_time(e1) / its)
+        return ms_per_step, float(np.mean(kern_ms)), wall, n
 
     if args.copy_mb > 0:
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
@@ -129,39 +164,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
-
-    # The dominant kernel: the fused step launches of one fe_advance call
-    # (same jobs, same plan), timed with HIP events on the same stream.
-    batch = fe.Batch(prior, specs, stream=stream)
-    its = max(j.iterations for j in cfg["jobs"])
-    kern_ms = []
-    for _ in range(max(1, args.steps)):
-        batch.begin()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        batch.advance([j.iterations for j in cfg["jobs"]])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        kern_ms.append(e0.elapsed_time(e1) / its)
-    launch_ms = float(np.mean(kern_ms))
-
-    px_it = sum(j.height * j.width * j.iterations for j in cfg["jobs"])
-    px_per_launch = sum(j.height * j.width for j in cfg["jobs"])
+    ms_per_step, launch_ms, wall, n = measure("fp32", args.steps, args.warmup)
     value = px_it / (ms_per_step * 1e-3) / 1e6
     achieved = flops_per_px_it(m, nf) * px_per_launch / (launch_ms * 1e-3) / 1e12
     traffic = recorded_traffic(args)
@@ -181,13 +184,25 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": "fused_step_kernel<7,3> (one launch = one iteration of "
-                               "all %d jobs)" % n,
+                     "kernel": "fused_step_kernel<7,MathF32<7,3>> (one launch = one "
+                               "iteration of all %d jobs)" % n,
                      "launch_us": round(launch_ms * 1e3, 2),
                      "flop_per_launch": flops_per_px_it(m, nf) * px_per_launch},
         "hbm_algorithmic_GBs": round(hbm_bytes_per_px_it() * px_per_launch
                                      / (launch_ms * 1e-3) / 1e9, 1),
     }
+    if not args.no_mixed:
+        mixed = {}
+        for prec in ("bf16", "fp16"):
+            ms_p, launch_p, _, _ = measure(prec, args.steps, 1)
+            ach = flops_per_px_it(m, nf) * px_per_launch / (launch_p * 1e-3) / 1e12
+            mixed[prec] = {"value": round(px_it / (ms_p * 1e-3) / 1e6, 2),
+                           "unit": "Mpixel-iter/s", "ms_per_step": round(ms_p, 4),
+                           "images_per_s": round(n / (ms_p * 1e-3), 2),
+                           "launch_us": round(launch_p * 1e3, 2),
+                           "achieved_TFLOPs": round(ach, 3),
+                           "frac_of_mfma_peak": round(ach / MFMA16_PEAK_TFLOPS, 4)}
+        result["mixed_precision"] = mixed
     if not args.no_cpu:
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
         result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)

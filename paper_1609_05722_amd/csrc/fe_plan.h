@@ -21,6 +21,8 @@ struct FusedBank {
     float *adj = nullptr;        // adjoint B operands x 2alpha [nfb][4][ntb][64]
     float *lastf = nullptr;      // last tap, forward           [nfb][4][64]
     float *lasta = nullptr;      // last tap x 2alpha, adjoint  [nfb][4][64]
+    void *bf_fwd = nullptr, *bf_adj = nullptr;  // bfloat16 operand tables
+    void *h_fwd = nullptr, *h_adj = nullptr;    // float16 operand tables
 };
 
 // How a batch is cut into workgroup tiles: every job's image is split into
@@ -46,9 +48,9 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf,
 void fused_release(FusedBank *b);
 void make_plan(int m, const AdvanceItem *items, int n, Plan *plan);
 size_t fused_table_bytes(int n);
-// Enqueues the job table and max(count) step launches; job i is advanced by
-// items[i].count iterations.
-hipError_t run_fused(const FusedBank &bank, const Plan &plan, const AdvanceItem *items,
-                     int n, void *plan_ws, hipStream_t s);
+// Enqueues the job table and max(count) step launches per precision group;
+// job i is advanced by items[i].count iterations.
+hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
+                     hipStream_t s);
 
 }  // namespace fe

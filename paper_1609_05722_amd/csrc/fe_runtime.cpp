@@ -90,8 +90,6 @@ fe_status check_job(const fe_ctx *c, const fe_job &j, int idx)
     if (j.precision != FE_PREC_FP32 && j.precision != FE_PREC_BF16 &&
         j.precision != FE_PREC_FP16)
         return fail(FE_ERR_INVALID, "job %d: unknown precision %d", idx, j.precision);
-    if (j.precision != FE_PREC_FP32)
-        return fail(FE_ERR_UNSUPPORTED, "job %d: reduced-precision contractions are not built", idx);
     return FE_OK;
 }
 
@@ -178,9 +176,7 @@ fe_status enqueue_advance(const fe_ctx *c, const fe_job *jobs, float *const *sta
 {
     std::vector<fe::AdvanceItem> items(n);
     for (int i = 0; i < n; ++i) items[i] = {&jobs[i], states[i], done[i], count[i]};
-    fe::Plan plan;
-    fe::make_plan(c->m, items.data(), n, &plan);
-    hipError_t e = fe::run_fused(c->fused, plan, items.data(), n, table, s);
+    hipError_t e = fe::run_fused(c->fused, items.data(), n, table, s);
     if (e != hipSuccess) return hip_fail(e, "fused step");
     return FE_OK;
 }

@@ -31,9 +31,19 @@
 // mirror each border pixel (the transpose of the symmetric extension).
 // No atomics: every sum is taken in a fixed order, so results are bitwise
 // reproducible and independent of what else is in the batch.
+//
+// Reduced precision (FE_PREC_BF16 / FE_PREC_FP16): both contractions use
+// v_mfma_f32_16x16x32_{bf16,f16} (operands rounded to nearest even, FP32
+// accumulation).  K = 32 per instruction, so all m^2 taps of the forward bank
+// fit in ceil(m^2 / 32) k-steps (no VALU tap) and the adjoint takes the
+// filters 32 at a time, its tap blocks covering all m^2 taps.  The adjoint's
+// filter order is permuted so that the forward accumulators are again its
+// A operand without data movement.  The influence, the collapse, the
+// inertial step and the prox stay FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 #include <vector>
 
@@ -45,6 +55,9 @@ namespace fe {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // Global-memory float.  Pointers read out of the job table are generic;
 // accesses through them would compile to FLAT instructions, which also
 // count against the LDS wait counter and would make every LDS wait wait for
@@ -119,13 +132,211 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// ---------------------------------------------------------------------------
+// Block arithmetic, FP32: forward and adjoint on v_mfma_f32_16x16x4_f32.
+// Operand tables (one float per lane per register slot):
+//   t0 forward A   [KF][NFB][64]      A[filter 16fb + l%16][tap 4s + l/16]
+//   t1 adjoint B   [NFB][4][NTB][64]  B[k: filter 16fb + 4(l/16) + j][tap 16nb + l%16] * 2 alpha
+//   t2 last tap    [NFB][4][64]       tap m^2-1 of filter 16fb + 4(l/16) + j
+//   t3 last tap    [NFB][4][64]       the same times 2 alpha
 template <int M, int NFB>
+struct MathF32 {
+    using G = Geo<M>;
+    float afwd[G::KF][NFB];
+    float badj[NFB][4][G::NTB];
+    float lastf[NFB][4], lasta[NFB][4];
+    int boff[G::KF], loff, perm16, perm32;
+    struct Acc {
+        f32x4 z[NFB];
+        float ul;
+    };
+
+    __device__ void load(const void *t0, const void *t1, const void *t2, const void *t3,
+                         int lane)
+    {
+        const float *fwd_tab = (const float *)t0, *adj_tab = (const float *)t1;
+        const float *lastf_tab = (const float *)t2, *lasta_tab = (const float *)t3;
+        const int p = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < G::KF; ++s)
+#pragma unroll
+            for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int nb = 0; nb < G::NTB; ++nb)
+                    badj[fb][j][nb] = adj_tab[((fb * 4 + j) * G::NTB + nb) * 64 + lane];
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                lastf[fb][j] = lastf_tab[(fb * 4 + j) * 64 + lane];
+                lasta[fb][j] = lasta_tab[(fb * 4 + j) * 64 + lane];
+            }
+        // LDS offsets of the forward B operand: tap 4s + g at pixel p
+#pragma unroll
+        for (int s = 0; s < G::KF; ++s) {
+            const int t = 4 * s + g;
+            boff[s] = (t / M) * G::US + (t % M) + p;
+        }
+        loff = (M - 1) * G::US + (M - 1) + p;
+        perm16 = (lane ^ 16) << 2;
+        perm32 = (lane ^ 32) << 2;
+    }
+
+    // Z^T[filter][px] for the block whose top-left u sample is Ub[0].
+    __device__ __forceinline__ void forward(const float *Ub, Acc &a) const
+    {
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb) a.z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < G::KF; ++s) {
+            const float b = Ub[boff[s]];
+#pragma unroll
+            for (int fb = 0; fb < NFB; ++fb)
+                a.z[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afwd[s][fb], b, a.z[fb], 0, 0, 0);
+        }
+        a.ul = Ub[loff];
+    }
+
+    // Influence, adjoint, tap contributions C[px][tap] into the scratch.
+    template <bool MASK>
+    __device__ __forceinline__ void adjoint(const Acc &a, bool inside, int p, int g,
+                                            float *Sw) const
+    {
+        f32x4 c[G::NTB];
+#pragma unroll
+        for (int nb = 0; nb < G::NTB; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float part = 0.0f;
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float zz = fmaf(lastf[fb][j], a.ul, a.z[fb][j]);
+                float phi = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
+                if (MASK) phi = inside ? phi : 0.0f;
+#pragma unroll
+                for (int nb = 0; nb < G::NTB; ++nb)
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
+                part = fmaf(lasta[fb][j], phi, part);
+            }
+        }
+        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm16, __float_as_int(part)));
+        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm32, __float_as_int(part)));
+        // C[px = 4g + jj][tap = 16 nb + p] -> scratch row = tap, column = px
+#pragma unroll
+        for (int nb = 0; nb < G::NTB; ++nb)
+            *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
+        if (g == 0) Sw[G::LAST_ROW * G::SW + G::SPAD + p] = part;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Block arithmetic, BF16 or FP16 operands (P), v_mfma_f32_16x16x32_*:
+// lane l supplies A[l % 16][8 (l/16) + e] and B[8 (l/16) + e][l % 16],
+// e = 0..7, as 8 packed values.  Tables (8 values of P per lane per slot):
+//   t0 forward A   [KS][NFB][64][8]   A[filter 16fb + l%16][tap 32s + 8(l/16) + e]
+//   t1 adjoint B   [KA][NTBP][64][8]  B[k = 8(l/16) + e][tap 16nb + l%16] * 2 alpha,
+//                  k standing for filter 16 (2s + e/4) + 4 (l/16) + e%4
+template <int M, int NFB, typename P>
+struct MathP16 {
+    using G = Geo<M>;
+    typedef P vec8 __attribute__((ext_vector_type(8)));
+    static constexpr int KS = (G::T + 31) / 32;    // forward k-steps
+    static constexpr int KA = (NFB + 1) / 2;       // adjoint k-steps (32 filters)
+    static constexpr int NTBP = (G::T + 15) / 16;  // adjoint tap blocks
+    u32x4 afwd[KS][NFB];
+    u32x4 badj[KA][NTBP];
+    int boff[KS][8];
+    struct Acc {
+        f32x4 z[NFB];
+    };
+
+    __device__ void load(const void *t0, const void *t1, const void *, const void *, int lane)
+    {
+        const u32x4 *fwd_tab = (const u32x4 *)t0, *adj_tab = (const u32x4 *)t1;
+        const int p = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
+#pragma unroll
+        for (int s = 0; s < KA; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NTBP; ++nb) badj[s][nb] = adj_tab[(s * NTBP + nb) * 64 + lane];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int t = 32 * s + 8 * g + e;
+                // padded taps read tap 0 (finite; its weight is zero)
+                boff[s][e] = t < G::T ? (t / M) * G::US + (t % M) + p : p;
+            }
+    }
+
+    __device__ __forceinline__ void forward(const float *Ub, Acc &a) const
+    {
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb) a.z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            vec8 b;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[e] = (P)Ub[boff[s][e]];
+#pragma unroll
+            for (int fb = 0; fb < NFB; ++fb)
+                a.z[fb] = mfma(__builtin_bit_cast(vec8, afwd[s][fb]), b, a.z[fb]);
+        }
+    }
+
+    template <bool MASK>
+    __device__ __forceinline__ void adjoint(const Acc &a, bool inside, int p, int g,
+                                            float *Sw) const
+    {
+        vec8 phi[KA];
+#pragma unroll
+        for (int s = 0; s < KA; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int fb = 2 * s + e / 4;
+                float ph = 0.0f;
+                if (fb < NFB) {
+                    const float zz = a.z[fb][e % 4];
+                    ph = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
+                    if (MASK) ph = inside ? ph : 0.0f;
+                }
+                phi[s][e] = (P)ph;
+            }
+        f32x4 c[NTBP];
+#pragma unroll
+        for (int nb = 0; nb < NTBP; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KA; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NTBP; ++nb)
+                c[nb] = mfma(phi[s], __builtin_bit_cast(vec8, badj[s][nb]), c[nb]);
+#pragma unroll
+        for (int nb = 0; nb < NTBP; ++nb)
+            if (16 * nb + 15 < G::T || 16 * nb + p < G::T)
+                *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
+    }
+
+    static __device__ __forceinline__ f32x4 mfma(vec8 a, vec8 b, f32x4 c)
+    {
+        if constexpr (std::is_same<P, __bf16>::value)
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int M, typename Math>
 __global__ __launch_bounds__(kThreads)
 void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
-                       const float *__restrict__ fwd_tab,
-                       const float *__restrict__ adj_tab,
-                       const float *__restrict__ lastf_tab,
-                       const float *__restrict__ lasta_tab,
+                       const void *__restrict__ t0, const void *__restrict__ t1,
+                       const void *__restrict__ t2, const void *__restrict__ t3,
                        int iter, int ty_max)
 {
     using G = Geo<M>;
@@ -162,36 +373,6 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *Hr = S + (size_t)kWaves * G::SROWS * G::SW;     // HR x M x QW
     float *Sw = S + (size_t)wave * G::SROWS * G::SW;
 
-    // ---- operand tables into registers -----------------------------------
-    float afwd[G::KF][NFB];
-#pragma unroll
-    for (int s = 0; s < G::KF; ++s)
-#pragma unroll
-        for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
-    float badj[NFB][4][G::NTB];
-#pragma unroll
-    for (int fb = 0; fb < NFB; ++fb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int nb = 0; nb < G::NTB; ++nb)
-                badj[fb][j][nb] = adj_tab[((fb * 4 + j) * G::NTB + nb) * 64 + lane];
-    float lastf[NFB][4], lasta[NFB][4];
-#pragma unroll
-    for (int fb = 0; fb < NFB; ++fb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            lastf[fb][j] = lastf_tab[(fb * 4 + j) * 64 + lane];
-            lasta[fb][j] = lasta_tab[(fb * 4 + j) * 64 + lane];
-        }
-    // LDS offsets of the forward B operand: tap 4s + g at pixel p.
-    int boff[G::KF];
-#pragma unroll
-    for (int s = 0; s < G::KF; ++s) {
-        const int t = 4 * s + g;
-        boff[s] = (t / M) * G::US + (t % M) + p;
-    }
-    const int loff = (M - 1) * G::US + (M - 1) + p;  // last tap
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
     // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
     // block column xr + R; hoff: H offset of (a, xr); valid: task exists.
@@ -206,7 +387,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         hoff[rr] = a * kQW + xr;
         xrr[rr] = ok ? xr : -1000;   // never a valid column when the task is absent
     }
-    const int perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;
+    Math mth;
+    mth.load(t0, t1, t2, t3, lane);
 
     // ---- zero this wave's scratch (its pad columns stay zero) -------------
     for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
@@ -224,58 +406,22 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int nq = ty + 2 * R;                 // q-rows of the tile
     const int nsteps = (nq + kWaves - 1) / kWaves;
 
-    // ---- one 16-pixel block: forward bank into z (matrix cores) -----------
-    auto forward = [&](int qr, int k, f32x4 (&z)[NFB], float &ul) {
-        const float *Ub = U + qr * G::US + 16 * k;
-#pragma unroll
-        for (int fb = 0; fb < NFB; ++fb) z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < G::KF; ++s) {
-            const float b = Ub[boff[s]];
-#pragma unroll
-            for (int fb = 0; fb < NFB; ++fb)
-                z[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afwd[s][fb], b, z[fb], 0, 0, 0);
-        }
-        ul = Ub[loff];
+    using Acc = typename Math::Acc;
+    // ---- one 16-pixel block: forward bank (matrix cores) ------------------
+    auto forward = [&](int qr, int k, Acc &acc) {
+        mth.forward(U + qr * G::US + 16 * k, acc);
     };
     // ---- influence, adjoint bank, tap contributions into the scratch ------
-    auto adjoint_impl = [&](auto mask_tag, int k, const f32x4 (&z)[NFB], float ul) {
-        constexpr bool MASK = decltype(mask_tag)::value;
-        const int qx = x0 - R + 16 * k + p;
-        const bool inside = qx >= 0 && qx < W;
-        f32x4 c[G::NTB];
-#pragma unroll
-        for (int nb = 0; nb < G::NTB; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float part = 0.0f;
-#pragma unroll
-        for (int fb = 0; fb < NFB; ++fb) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float zz = fmaf(lastf[fb][j], ul, z[fb][j]);
-                float phi = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
-                if (MASK) phi = inside ? phi : 0.0f;
-#pragma unroll
-                for (int nb = 0; nb < G::NTB; ++nb)
-                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
-                part = fmaf(lasta[fb][j], phi, part);
-            }
-        }
-        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm16, __float_as_int(part)));
-        part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm32, __float_as_int(part)));
-        // C[px = 4g + jj][tap = 16 nb + p] -> scratch row = tap, column = px
-#pragma unroll
-        for (int nb = 0; nb < G::NTB; ++nb)
-            *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
-        if (g == 0) Sw[G::LAST_ROW * G::SW + G::SPAD + p] = part;
-    };
     // Pixels of block k outside the image carry psi = 0 (the adjoint's
     // input vanishes off the image); blocks wholly inside skip the mask.
-    auto adjoint = [&](int k, const f32x4 (&z)[NFB], float ul) {
+    auto adjoint = [&](int k, const Acc &acc) {
         const int q0 = x0 - R + 16 * k;
-        if (q0 >= 0 && q0 + 15 < W)
-            adjoint_impl(std::integral_constant<bool, false>{}, k, z, ul);
-        else
-            adjoint_impl(std::integral_constant<bool, true>{}, k, z, ul);
+        if (q0 >= 0 && q0 + 15 < W) {
+            mth.template adjoint<false>(acc, true, p, g, Sw);
+        } else {
+            const int qx = q0 + p;
+            mth.template adjoint<true>(acc, qx >= 0 && qx < W, p, g, Sw);
+        }
     };
     // ---- horizontal collapse of block k into the q-row's H slot -----------
     //   H[a][16k + xr] (+)= sum_b C[xr + R - b][(a, b)]; the first block to
@@ -355,19 +501,18 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             const int qy = y0 - R + qr;
             if (qr < nq && qy >= 0 && qy < H) {
                 float *Hs = Hr + (size_t)(qr % G::HR) * M * kQW;
-                f32x4 z[NFB];
-                float ul;
+                Acc acc;
                 // software pipeline: the collapse of block k - 1 (LDS, VALU)
                 // is issued next to the forward MFMAs of block k
-                forward(qr, 0, z, ul);
-                adjoint(0, z, ul);
+                forward(qr, 0, acc);
+                adjoint(0, acc);
 #pragma unroll
                 for (int k = 1; k < kQB; ++k) {
                     lds_order();
-                    forward(qr, k, z, ul);
+                    forward(qr, k, acc);
                     collapse(Hs, k - 1);
                     lds_order();
-                    adjoint(k, z, ul);
+                    adjoint(k, acc);
                 }
                 lds_order();
                 collapse(Hs, kQB - 1);
@@ -394,22 +539,77 @@ __global__ void write_jobs_kernel(JobChunk c, JobDesc *dst)
 
 int nfb_for(int nf) { return (nf + 15) / 16; }
 
-template <int M, int NFB>
-hipError_t launch_step(const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
+template <int M, typename Math>
+hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, int ntiles,
                        int iter, int ty_max, hipStream_t s)
 {
     const size_t bytes = lds_bytes<M>(ty_max);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, NFB>,
+        hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes<M>(kMaxTileRows));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    fused_step_kernel<M, NFB><<<ntiles, kThreads, bytes, s>>>(jobs, njobs, b.fwd, b.adj, b.lastf,
-                                                              b.lasta, iter, ty_max);
+    fused_step_kernel<M, Math><<<ntiles, kThreads, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
+                                                               tabs[2], tabs[3], iter, ty_max);
     return hipGetLastError();
+}
+
+template <int M, int NFB>
+hipError_t launch_prec(int prec, const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
+                       int iter, int ty_max, hipStream_t s)
+{
+    if (prec == FE_PREC_BF16) {
+        const void *t[4] = {b.bf_fwd, b.bf_adj, nullptr, nullptr};
+        return launch_step<M, MathP16<M, NFB, __bf16>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+    }
+    if (prec == FE_PREC_FP16) {
+        const void *t[4] = {b.h_fwd, b.h_adj, nullptr, nullptr};
+        return launch_step<M, MathP16<M, NFB, _Float16>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+    }
+    const void *t[4] = {b.fwd, b.adj, b.lastf, b.lasta};
+    return launch_step<M, MathF32<M, NFB>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+}
+
+hipError_t launch_any(int prec, const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
+                      int iter, int ty_max, hipStream_t s)
+{
+#define FE_STEP(MM, NB) return launch_prec<MM, NB>(prec, b, jobs, njobs, ntiles, iter, ty_max, s)
+    switch (b.m * 10 + b.nfb) {
+    case 31: FE_STEP(3, 1);
+    case 32: FE_STEP(3, 2);
+    case 33: FE_STEP(3, 3);
+    case 34: FE_STEP(3, 4);
+    case 51: FE_STEP(5, 1);
+    case 52: FE_STEP(5, 2);
+    case 53: FE_STEP(5, 3);
+    case 54: FE_STEP(5, 4);
+    case 71: FE_STEP(7, 1);
+    case 72: FE_STEP(7, 2);
+    case 73: FE_STEP(7, 3);
+    case 74: FE_STEP(7, 4);
+    default: return hipErrorInvalidValue;
+    }
+#undef FE_STEP
+}
+
+// Round to nearest even: float -> bfloat16 bits (finite inputs).
+uint16_t bf16_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+uint16_t f16_bits(float x)
+{
+    _Float16 h = (_Float16)x;  // round to nearest even
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
 }
 
 }  // namespace
@@ -444,9 +644,46 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
                 lastf[(fb * 4 + j) * 64 + l] = tap(f, T - 1);
                 lasta[(fb * 4 + j) * 64 + l] = a2(f) * tap(f, T - 1);
             }
+    // BF16 / FP16 operands (16x16x32 lane layout; see MathP16)
+    const int KS = (T + 31) / 32, KA = (NFB + 1) / 2, NTBP = (T + 15) / 16;
+    std::vector<float> pf((size_t)KS * NFB * 64 * 8), pa((size_t)KA * NTBP * 64 * 8);
+    for (int s = 0; s < KS; ++s)
+        for (int fb = 0; fb < NFB; ++fb)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e)
+                    pf[((s * NFB + fb) * 64 + l) * 8 + e] =
+                        tap(fb * 16 + (l & 15), 32 * s + 8 * (l >> 4) + e);
+    for (int s = 0; s < KA; ++s)
+        for (int nb = 0; nb < NTBP; ++nb)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int fb = 2 * s + e / 4;
+                    const int f = 16 * fb + 4 * (l >> 4) + (e & 3), t = 16 * nb + (l & 15);
+                    pa[((s * NTBP + nb) * 64 + l) * 8 + e] =
+                        (fb < NFB && t < T) ? a2(f) * tap(f, t) : 0.0f;
+                }
+    std::vector<uint16_t> bff(pf.size()), bfa(pa.size()), hf(pf.size()), ha(pa.size());
+    for (size_t i = 0; i < pf.size(); ++i) {
+        bff[i] = bf16_bits(pf[i]);
+        hf[i] = f16_bits(pf[i]);
+    }
+    for (size_t i = 0; i < pa.size(); ++i) {
+        bfa[i] = bf16_bits(pa[i]);
+        ha[i] = f16_bits(pa[i]);
+    }
     out->m = m;
     out->nf = nf;
     out->nfb = NFB;
+    auto up16 = [](const std::vector<uint16_t> &h, void **d) {
+        hipError_t e = hipMalloc(d, h.size() * 2);
+        if (e == hipSuccess) e = hipMemcpy(*d, h.data(), h.size() * 2, hipMemcpyHostToDevice);
+        return e;
+    };
+    hipError_t e16 = up16(bff, &out->bf_fwd);
+    if (e16 == hipSuccess) e16 = up16(bfa, &out->bf_adj);
+    if (e16 == hipSuccess) e16 = up16(hf, &out->h_fwd);
+    if (e16 == hipSuccess) e16 = up16(ha, &out->h_adj);
+    if (e16 != hipSuccess) return e16;
     hipError_t e = hipMalloc((void **)&out->fwd, fwd.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&out->adj, adj.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&out->lastf, lastf.size() * sizeof(float));
@@ -466,7 +703,12 @@ void fused_release(FusedBank *b)
     (void)hipFree(b->adj);
     (void)hipFree(b->lastf);
     (void)hipFree(b->lasta);
+    (void)hipFree(b->bf_fwd);
+    (void)hipFree(b->bf_adj);
+    (void)hipFree(b->h_fwd);
+    (void)hipFree(b->h_adj);
     b->fwd = b->adj = b->lastf = b->lasta = nullptr;
+    b->bf_fwd = b->bf_adj = b->h_fwd = b->h_adj = nullptr;
 }
 
 // Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
@@ -513,65 +755,60 @@ void make_plan(int m, const AdvanceItem *items, int n, Plan *plan)
 size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(JobDesc); }
 size_t fused_table_bytes(int n) { return (size_t)std::max(n, 1) * sizeof(JobDesc); }
 
-hipError_t run_fused(const FusedBank &bank, const Plan &plan, const AdvanceItem *items, int n,
-                     void *plan_ws, hipStream_t s)
+hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
+                     hipStream_t s)
 {
-    JobDesc *dj = (JobDesc *)plan_ws;
-    int max_it = 0, base = 0;
-    for (int c0 = 0; c0 < n; c0 += kChunk) {
-        JobChunk ch{};
-        ch.first = c0;
-        ch.count = std::min(kChunk, n - c0);
-        for (int i = 0; i < ch.count; ++i) {
-            const AdvanceItem &it = items[c0 + i];
-            const fe_job &j = *it.job;
-            JobDesc &d = ch.d[i];
-            const size_t plane = (size_t)j.height * j.width;
-            d.counts = j.counts;
-            d.ua = it.state;
-            d.ub = it.state + plane;
-            d.H = j.height;
-            d.W = j.width;
-            d.ntx = plan.jobs_ntx[c0 + i];
-            d.nty = plan.jobs_nty[c0 + i];
-            d.tile_base = base;
-            base += d.ntx * d.nty;
-            d.iters = std::max(it.count, 0);
-            d.it0 = it.done;
-            d.tau = j.tau;
-            d.gamma = j.gamma;
-            d.tl = j.tau * j.lambda;
-            d.data_term = j.data_term == FE_DATA_AUTO
-                              ? (j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV)
-                              : j.data_term;
-            max_it = std::max(max_it, d.iters);
+    // Jobs run in groups of equal precision (one kernel per precision); each
+    // group has its own slice of the job table and its own plan.
+    JobDesc *table = (JobDesc *)plan_ws;
+    int slot = 0;
+    for (int prec = FE_PREC_FP32; prec <= FE_PREC_FP16; ++prec) {
+        std::vector<AdvanceItem> grp;
+        for (int i = 0; i < n; ++i)
+            if (items[i].job->precision == prec && items[i].count > 0) grp.push_back(items[i]);
+        if (grp.empty()) continue;
+        const int gn = (int)grp.size();
+        Plan plan;
+        make_plan(bank.m, grp.data(), gn, &plan);
+        JobDesc *dj = table + slot;
+        slot += gn;
+        int max_it = 0, base = 0;
+        for (int c0 = 0; c0 < gn; c0 += kChunk) {
+            JobChunk ch{};
+            ch.first = c0;
+            ch.count = std::min(kChunk, gn - c0);
+            for (int i = 0; i < ch.count; ++i) {
+                const AdvanceItem &it = grp[c0 + i];
+                const fe_job &j = *it.job;
+                JobDesc &d = ch.d[i];
+                const size_t plane = (size_t)j.height * j.width;
+                d.counts = j.counts;
+                d.ua = it.state;
+                d.ub = it.state + plane;
+                d.H = j.height;
+                d.W = j.width;
+                d.ntx = plan.jobs_ntx[c0 + i];
+                d.nty = plan.jobs_nty[c0 + i];
+                d.tile_base = base;
+                base += d.ntx * d.nty;
+                d.iters = it.count;
+                d.it0 = it.done;
+                d.tau = j.tau;
+                d.gamma = j.gamma;
+                d.tl = j.tau * j.lambda;
+                d.data_term = j.data_term == FE_DATA_AUTO
+                                  ? (j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV)
+                                  : j.data_term;
+                max_it = std::max(max_it, d.iters);
+            }
+            write_jobs_kernel<<<1, kChunk, 0, s>>>(ch, dj);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
-        write_jobs_kernel<<<1, kChunk, 0, s>>>(ch, dj);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (plan.ntiles == 0) return hipSuccess;
-    const int nfb = nfb_for(bank.nf);
-    for (int it = 0; it < max_it; ++it) {
-        hipError_t e = hipErrorInvalidValue;
-#define FE_STEP(MM, NB) e = launch_step<MM, NB>(bank, dj, n, plan.ntiles, it, plan.tile_h, s)
-        switch (bank.m * 10 + nfb) {
-        case 31: FE_STEP(3, 1); break;
-        case 32: FE_STEP(3, 2); break;
-        case 33: FE_STEP(3, 3); break;
-        case 34: FE_STEP(3, 4); break;
-        case 51: FE_STEP(5, 1); break;
-        case 52: FE_STEP(5, 2); break;
-        case 53: FE_STEP(5, 3); break;
-        case 54: FE_STEP(5, 4); break;
-        case 71: FE_STEP(7, 1); break;
-        case 72: FE_STEP(7, 2); break;
-        case 73: FE_STEP(7, 3); break;
-        case 74: FE_STEP(7, 4); break;
-        default: break;
+        for (int it = 0; it < max_it; ++it) {
+            hipError_t e = launch_any(prec, bank, dj, gn, plan.ntiles, it, plan.tile_h, s);
+            if (e != hipSuccess) return e;
         }
-#undef FE_STEP
-        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

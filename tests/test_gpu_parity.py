@@ -200,3 +200,71 @@ def test_stepping_matches_denoise_and_resumes(fe, torch):
     torch.cuda.synchronize()
     for (x0, u0), (x1, u1) in zip(ref, out3):
         assert torch.equal(u0, u1) and torch.equal(x0, x1)
+
+
+def _psnr(xh, x, peak):
+    return 10.0 * np.log10(peak ** 2 / np.mean((xh - x) ** 2))
+
+
+# Reduced-precision contractions (BF16 / FP16 operands, FP32 accumulation):
+# reported against the FP64 oracle as max and RMS error of u_hat and the
+# PSNR change of x_hat; the bar is |dPSNR| <= 0.05 dB, and the per-pixel
+# errors stay within what operand rounding allows (8 and 11 significant
+# bits on O(1) filter responses).
+_MIXED_TOL = {"bf16": 5e-2, "fp16": 5e-3}
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("peak", [1.0, 8.0])
+def test_mixed_precision_error_report(fe, torch, precision, peak):
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    from synth.workloads import data_term_for_peak, lambda_for_peak
+    x, y = noisy_pair(1, 101, 160, 144, peak)
+    lam, dt = lambda_for_peak(peak), data_term_for_peak(peak)
+    ug, xg = _run(fe, torch, prior, y, lam, tau, gamma, 200, dt, precision=precision)
+    uo, xo = oracle.denoise(y, k, a, lam, tau, gamma, 200, dt)
+    err = np.abs(ug - uo)
+    dpsnr = _psnr(xg, x, peak) - _psnr(xo, x, peak)
+    print("precision %s peak %g: max|du| %.3e rms %.3e dPSNR %+.4f dB"
+          % (precision, peak, err.max(), np.sqrt(np.mean(err ** 2)), dpsnr), flush=True)
+    assert abs(dpsnr) <= 0.05
+    assert err.max() <= _MIXED_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_mixed_precision_full_size(fe, torch, precision):
+    """512 x 512, peak 2 (I-div), 200 iterations, against the FP64 oracle."""
+    cfg = fp32_config()
+    j = [jj for jj in cfg["jobs"] if jj.peak == 2.0][0]
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    x, y = j.arrays()
+    ug, xg = _run(fe, torch, prior, y, j.lam, tau, gamma, j.iterations, j.data_term,
+                  precision=precision)
+    uo, xo = oracle.denoise(y, k, a, j.lam, tau, gamma, j.iterations, j.data_term)
+    err = np.abs(ug - uo)
+    dpsnr = _psnr(xg, x, j.peak) - _psnr(xo, x, j.peak)
+    print("precision %s 512x512 peak 2: max|du| %.3e rms %.3e dPSNR %+.4f dB"
+          % (precision, err.max(), np.sqrt(np.mean(err ** 2)), dpsnr), flush=True)
+    assert abs(dpsnr) <= 0.05
+    assert err.max() <= _MIXED_TOL[precision]
+
+
+def test_mixed_precision_batch_equals_alone(fe, torch):
+    """A reduced-precision job gives bitwise the same result alone and in a
+    batch that mixes precisions, sizes and data terms."""
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    specs = []
+    for i, (H, W, pk, pr) in enumerate([(90, 70, 1.0, "bf16"), (64, 200, 8.0, "fp16"),
+                                        (128, 128, 4.0, "fp32"), (33, 47, 2.0, "bf16")]):
+        _, y = noisy_pair(700 + i, 800 + i, H, W, pk)
+        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, 21, tau, gamma,
+                                data_term="auto", peak=pk, precision=pr, want_anscombe=True))
+    mix = fe.denoise_jobs(prior, specs)
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        (x1, u1), = fe.denoise_jobs(prior, [s])
+        torch.cuda.synchronize()
+        assert torch.equal(u1, mix[i][1]) and torch.equal(x1, mix[i][0])
