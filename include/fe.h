@@ -141,6 +141,22 @@ fe_status fe_advance(const fe_ctx *ctx, const fe_job *jobs, float *const *states
 fe_status fe_end(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
                  const int32_t *done, int32_t n, void *hip_stream);
 
+/* ---- binning variant (Section 4: 3 x 3 ones kernel, bilinear upscaling;
+ * the data term follows the binned image's peak, eq. 3.7) ----------------
+ * Each job's counts are summed over non-overlapping 3 x 3 blocks (the image
+ * extended half-sample symmetrically to a multiple of 3), giving a
+ * ceil(H/3) x ceil(W/3) image with nine times the peak; that image is
+ * denoised with the job's parameters (with FE_DATA_AUTO the data term is
+ * chosen for peak * 9; lambda applies to the binned problem); the result / 9
+ * is placed at the bin centres (3i + 1, 3j + 1) and upsampled bilinearly
+ * (constant beyond the outermost centres) into job.out (H x W).  If
+ * job.out_anscombe is not NULL its first ceil(H/3) * ceil(W/3) values receive
+ * the binned u_hat.  Requires ceil(H/3), ceil(W/3) >= r and H, W >= 2. */
+fe_status fe_binned_workspace_size(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
+                                   size_t *bytes);
+fe_status fe_denoise_binned(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
+                            void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Workspace bytes fe_energy_grad needs for an H x W image. */
 fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,
                                         int32_t width, size_t *bytes);

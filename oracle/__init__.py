@@ -50,6 +50,8 @@ def _signatures():
         "oracle_energy_grad": (d, [_dp, _dp, i, i, _dp, _dp, i, i, d, i,
                                    _dp]),
         "oracle_power_iteration": (d, [_dp, i, i, _dp, _dp, i, i, i]),
+        "oracle_bin3": (None, [_dp, i, i, _dp]),
+        "oracle_upsample3": (None, [_dp, i, i, i, i, _dp]),
     }
 
 
@@ -258,3 +260,32 @@ def set_threads(n):
         return int(n)
     except OSError:
         return None
+
+
+def bin3(y):
+    """Sums of the 3 x 3 blocks of the symmetrically extended image."""
+    y, py = _d(y)
+    H, W = y.shape
+    yb = np.empty(((H + 2) // 3, (W + 2) // 3))
+    _load().oracle_bin3(py, H, W, yb.ctypes.data_as(_dp))
+    return yb
+
+
+def upsample3(xb, H, W):
+    """Bilinear upscaling of xb / 9 (bin centres at 3i + 1) to H x W."""
+    xb, pxb = _d(xb)
+    x = np.empty((H, W))
+    _load().oracle_upsample3(pxb, xb.shape[0], xb.shape[1], int(H), int(W),
+                             x.ctypes.data_as(_dp))
+    return x
+
+
+def denoise_binned(counts, k, alpha, lam, tau, gamma, iters, data_term):
+    """The binning variant: bin, denoise the binned counts (eq. 3.7 with the
+    binned image's peak deciding the data term), upsample.  The binned
+    counts are integers, so they stay exact in float32.  Returns
+    (u_hat of the binned image, x_hat at full size)."""
+    y = np.asarray(counts, np.float32)
+    yb = bin3(y.astype(np.float64)).astype(np.float32)
+    ub, xb = denoise(yb, k, alpha, lam, tau, gamma, iters, data_term)
+    return ub, upsample3(xb, y.shape[0], y.shape[1])

@@ -373,3 +373,53 @@ double oracle_power_iteration(const double *x0, int H, int W, const double *k,
     free(x); free(z); free(y);
     return lam;
 }
+
+/* ---- binning variant (Section 4: 3 x 3 ones kernel, peak x 9, bilinear
+ * upscaling; eq. 3.7 with the peak of the binned image) ---------------------
+ * Readings: bins are the non-overlapping 3 x 3 blocks starting at (0, 0);
+ * an image whose side is not a multiple of 3 is first extended half-sample
+ * symmetrically, so every bin sums nine counts; the denoised bin value
+ * estimates the sum of nine intensities, so the per-pixel estimate is the
+ * bin value / 9, placed at the bin centre (3i + 1, 3j + 1) and interpolated
+ * bilinearly, constant beyond the outermost centres. */
+
+/* yb[i][j] = sum of the 3 x 3 block (3i.., 3j..) of the extended image;
+ * yb is ceil(H/3) x ceil(W/3). */
+void oracle_bin3(const double *y, int H, int W, double *yb)
+{
+    const long Hb = (H + 2) / 3, Wb = (W + 2) / 3;
+    for (long i = 0; i < Hb; ++i)
+        for (long j = 0; j < Wb; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    s += y[sym_index(3 * i + a, H) * W + sym_index(3 * j + b, W)];
+            yb[i * Wb + j] = s;
+        }
+}
+
+/* Bilinear upscaling of the per-pixel estimate xb / 9 to H x W. */
+void oracle_upsample3(const double *xb, int Hb, int Wb, int H, int W, double *x)
+{
+    for (long y = 0; y < H; ++y) {
+        double fy = (y - 1) / 3.0;
+        if (fy < 0.0) fy = 0.0;
+        if (fy > Hb - 1) fy = Hb - 1;
+        long i0 = (long)floor(fy);
+        if (i0 > Hb - 1) i0 = Hb - 1;
+        const long i1 = i0 + 1 < Hb ? i0 + 1 : Hb - 1;
+        const double wy = fy - i0;
+        for (long xx = 0; xx < W; ++xx) {
+            double fx = (xx - 1) / 3.0;
+            if (fx < 0.0) fx = 0.0;
+            if (fx > Wb - 1) fx = Wb - 1;
+            long j0 = (long)floor(fx);
+            if (j0 > Wb - 1) j0 = Wb - 1;
+            const long j1 = j0 + 1 < Wb ? j0 + 1 : Wb - 1;
+            const double wx = fx - j0;
+            const double v = (1.0 - wy) * ((1.0 - wx) * xb[i0 * Wb + j0] + wx * xb[i0 * Wb + j1])
+                             + wy * ((1.0 - wx) * xb[i1 * Wb + j0] + wx * xb[i1 * Wb + j1]);
+            x[y * W + xx] = v / 9.0;
+        }
+    }
+}

@@ -27,7 +27,8 @@ _DATA = {"auto": DATA_AUTO, "quadratic": DATA_QUADRATIC, "idiv": DATA_IDIV}
 
 EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
            "fe_state_bytes", "fe_begin", "fe_advance_workspace_size", "fe_advance",
-           "fe_end", "fe_energy_grad_workspace_size", "fe_energy_grad",
+           "fe_end", "fe_binned_workspace_size", "fe_denoise_binned",
+           "fe_energy_grad_workspace_size", "fe_energy_grad",
            "fe_last_error")
 
 
@@ -90,6 +91,11 @@ def library():
         lib.fe_advance.restype = i32
         lib.fe_end.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, i32, vp]
         lib.fe_end.restype = i32
+        lib.fe_binned_workspace_size.argtypes = [vp, ctypes.POINTER(_Job), i32,
+                                                 ctypes.POINTER(sz)]
+        lib.fe_binned_workspace_size.restype = i32
+        lib.fe_denoise_binned.argtypes = [vp, ctypes.POINTER(_Job), i32, vp, sz, vp]
+        lib.fe_denoise_binned.restype = i32
         lib.fe_last_error.argtypes = []
         lib.fe_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -223,6 +229,28 @@ def denoise_jobs(prior, specs, workspace=None, stream=None):
                 if t is not None:
                     t.record_stream(stream)
     return [(o, oa) for (_, o, oa) in keep]
+
+
+def denoise_binned_jobs(prior, specs, stream=None):
+    """fe_denoise_binned over several jobs (the binning variant).  Returns a
+    list of (x_hat H x W, binned u_hat or None); asynchronous."""
+    arr, keep = make_jobs(specs)
+    n = len(specs)
+    sz = ctypes.c_size_t()
+    _check(library().fe_binned_workspace_size(prior.handle, arr, n, ctypes.byref(sz)))
+    ws = alloc_workspace(sz.value, specs[0].counts.device if n else "cuda")
+    _check(library().fe_denoise_binned(prior.handle, arr, n, _ptr(ws), ws.numel(),
+                                       _stream_handle(stream)))
+    if stream is not None:
+        ws.record_stream(stream)
+    out = []
+    for (c, o, oa) in keep:
+        ub = None
+        if oa is not None:
+            Hb, Wb = (c.shape[0] + 2) // 3, (c.shape[1] + 2) // 3
+            ub = oa.view(-1)[:Hb * Wb].view(Hb, Wb)
+        out.append((o, ub))
+    return out
 
 
 def denoise(counts, prior, lam, iterations, tau, gamma, data_term="auto",

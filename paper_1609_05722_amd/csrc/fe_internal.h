@@ -38,6 +38,9 @@ hipError_t launch_anscombe_init(const float *counts, float *u0, float *u1,
                                 long n, hipStream_t s);
 hipError_t launch_inverse_anscombe(const float *u, float *out,
                                    float *out_anscombe, long n, hipStream_t s);
+hipError_t launch_bin3(const float *y, int H, int W, float *yb, hipStream_t s);
+hipError_t launch_upsample3(const float *xb, int Hb, int Wb, float *x, int H, int W,
+                            hipStream_t s);
 
 // ---- direct (non-MFMA) FP32 kernels (kernels_direct.hip) ------------------
 // psi_i = alpha_i rho'(K_i u) for all filters, written as nf planes of H*W.

@@ -361,6 +361,89 @@ fe_status fe_end(const fe_ctx *c, const fe_job *jobs, float *const *states,
     return enqueue_end(jobs, states, done, n, (hipStream_t)hip_stream);
 }
 
+// ---- binning variant ----------------------------------------------------
+namespace {
+struct BinnedLayout {
+    std::vector<fe_job> bjobs;          // the jobs on the binned images
+    std::vector<size_t> yb_off, xb_off; // binned counts and estimates
+    size_t inner_off = 0, inner_bytes = 0, total = 0;
+};
+
+fe_status binned_layout(const fe_ctx *c, const fe_job *jobs, int32_t n, BinnedLayout *L)
+{
+    const int r = radius(c);
+    size_t off = 0;
+    L->bjobs.assign(jobs, jobs + n);
+    L->yb_off.resize(n);
+    L->xb_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const int Hb = (jobs[i].height + 2) / 3, Wb = (jobs[i].width + 2) / 3;
+        if (Hb < r || Wb < r || jobs[i].height < 2 || jobs[i].width < 2)
+            return fail(FE_ERR_INVALID, "job %d: binned image %dx%d smaller than the filter radius",
+                        i, Hb, Wb);
+        const size_t b = align256((size_t)Hb * Wb * sizeof(float));
+        L->yb_off[i] = off;
+        off += b;
+        L->xb_off[i] = off;
+        off += b;
+        fe_job &bj = L->bjobs[i];
+        bj.height = Hb;
+        bj.width = Wb;
+        bj.peak = 9.0f * jobs[i].peak;  // the binned image's peak picks the data term
+    }
+    L->inner_off = off;
+    L->inner_bytes = layout_for(L->bjobs.data(), n).total;
+    L->total = off + L->inner_bytes;
+    return FE_OK;
+}
+}  // namespace
+
+fe_status fe_binned_workspace_size(const fe_ctx *c, const fe_job *jobs, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    fe_status st = check_batch(c, jobs, n);
+    if (st != FE_OK) return st;
+    BinnedLayout L;
+    st = binned_layout(c, jobs, n, &L);
+    if (st != FE_OK) return st;
+    *bytes = std::max<size_t>(L.total, 256);
+    return FE_OK;
+}
+
+fe_status fe_denoise_binned(const fe_ctx *c, const fe_job *jobs, int32_t n, void *workspace,
+                            size_t ws_bytes, void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st != FE_OK || n == 0) return st;
+    BinnedLayout L;
+    st = binned_layout(c, jobs, n, &L);
+    if (st != FE_OK) return st;
+    st = check_workspace(workspace, ws_bytes, L.total);
+    if (st != FE_OK) return st;
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *ws = (char *)workspace;
+    for (int i = 0; i < n; ++i) {
+        float *yb = (float *)(ws + L.yb_off[i]);
+        hipError_t e = fe::launch_bin3(jobs[i].counts, jobs[i].height, jobs[i].width, yb, s);
+        if (e != hipSuccess) return hip_fail(e, "bin3");
+        L.bjobs[i].counts = yb;
+        L.bjobs[i].out = (float *)(ws + L.xb_off[i]);
+        // out_anscombe (if given) receives the binned u_hat, Hb * Wb values
+    }
+    st = fe_denoise(c, L.bjobs.data(), n, ws + L.inner_off, L.inner_bytes, hip_stream);
+    if (st != FE_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        if (!jobs[i].out) continue;
+        hipError_t e = fe::launch_upsample3(L.bjobs[i].out, L.bjobs[i].height, L.bjobs[i].width,
+                                            jobs[i].out, jobs[i].height, jobs[i].width, s);
+        if (e != hipSuccess) return hip_fail(e, "upsample3");
+    }
+    return FE_OK;
+}
+
 fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)
 {
     if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");

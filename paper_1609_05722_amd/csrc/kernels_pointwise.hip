@@ -44,6 +44,52 @@ __global__ void inverse_anscombe_kernel(const float *__restrict__ u,
     }
 }
 
+__device__ __forceinline__ int sym1(int i, int n)
+{
+    if (i < 0) i = -1 - i;
+    if (i >= n) i = 2 * n - 1 - i;
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Binning (Section 4): sums of the non-overlapping 3 x 3 blocks of the
+// symmetrically extended image; binned image ceil(H/3) x ceil(W/3).
+__global__ void bin3_kernel(const float *__restrict__ y, int H, int W,
+                            float *__restrict__ yb, int Hb, int Wb)
+{
+    const long n = (long)Hb * Wb;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int i = (int)(q / Wb), j = (int)(q - (long)i * Wb);
+        float s = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            const long row = (long)sym1(3 * i + a, H) * W;
+            for (int b = 0; b < 3; ++b) s += y[row + sym1(3 * j + b, W)];
+        }
+        yb[q] = s;
+    }
+}
+
+// Bilinear upscaling of xb / 9 (the binned estimate of nine pixels'
+// intensity) from the bin centres (3i + 1, 3j + 1) to H x W; constant beyond
+// the outermost centres.
+__global__ void upsample3_kernel(const float *__restrict__ xb, int Hb, int Wb,
+                                 float *__restrict__ x, int H, int W)
+{
+    const long n = (long)H * W;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int yy = (int)(q / W), xx = (int)(q - (long)yy * W);
+        float fy = fminf(fmaxf((yy - 1) / 3.0f, 0.0f), (float)(Hb - 1));
+        float fx = fminf(fmaxf((xx - 1) / 3.0f, 0.0f), (float)(Wb - 1));
+        const int i0 = min((int)floorf(fy), Hb - 1), j0 = min((int)floorf(fx), Wb - 1);
+        const int i1 = min(i0 + 1, Hb - 1), j1 = min(j0 + 1, Wb - 1);
+        const float wy = fy - i0, wx = fx - j0;
+        const float top = (1.0f - wx) * xb[(long)i0 * Wb + j0] + wx * xb[(long)i0 * Wb + j1];
+        const float bot = (1.0f - wx) * xb[(long)i1 * Wb + j0] + wx * xb[(long)i1 * Wb + j1];
+        x[q] = ((1.0f - wy) * top + wy * bot) / 9.0f;
+    }
+}
+
 int grid_for(long n)
 {
     long b = (n + 255) / 256;
@@ -53,6 +99,20 @@ int grid_for(long n)
 }
 
 }  // namespace
+
+hipError_t launch_bin3(const float *y, int H, int W, float *yb, hipStream_t s)
+{
+    const int Hb = (H + 2) / 3, Wb = (W + 2) / 3;
+    bin3_kernel<<<grid_for((long)Hb * Wb), 256, 0, s>>>(y, H, W, yb, Hb, Wb);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample3(const float *xb, int Hb, int Wb, float *x, int H, int W,
+                            hipStream_t s)
+{
+    upsample3_kernel<<<grid_for((long)H * W), 256, 0, s>>>(xb, Hb, Wb, x, H, W);
+    return hipGetLastError();
+}
 
 hipError_t launch_anscombe_init(const float *counts, float *u0, float *u1,
                                 long n, hipStream_t s)

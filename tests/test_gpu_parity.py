@@ -268,3 +268,24 @@ def test_mixed_precision_batch_equals_alone(fe, torch):
         (x1, u1), = fe.denoise_jobs(prior, [s])
         torch.cuda.synchronize()
         assert torch.equal(u1, mix[i][1]) and torch.equal(x1, mix[i][0])
+
+
+@pytest.mark.parametrize("peak", [0.5, 1.0])
+@pytest.mark.parametrize("shape", [(96, 120), (101, 77)])
+def test_binned_variant(fe, torch, peak, shape):
+    """Binning: 3 x 3 sums, the denoiser on the binned counts with the data
+    term picked by the binned peak (0.5 -> 4.5: I-div; 1 -> 9: quadratic),
+    bilinear upsampling; against the oracle's binned pipeline."""
+    from synth.workloads import data_term_for_peak, lambda_for_peak
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    H, W = shape
+    x, y = noisy_pair(900 + H, 950 + W, H, W, peak)
+    lam = lambda_for_peak(9 * peak)
+    spec = fe.JobSpec(torch.from_numpy(y).cuda(), lam, 60, tau, gamma, data_term="auto",
+                      peak=peak, want_anscombe=True)
+    (xg, ubg), = fe.denoise_binned_jobs(prior, [spec])
+    torch.cuda.synchronize()
+    ub, xo = oracle.denoise_binned(y, k, a, lam, tau, gamma, 60, data_term_for_peak(9 * peak))
+    assert _rel_err(ubg.cpu().numpy().astype(np.float64), ub) <= TOL
+    assert _rel_err(xg.cpu().numpy().astype(np.float64), xo) <= TOL
