@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--iterations", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests per serving run (the full serving workload "
+                         "is python -m paper_1609_05722_amd.serving)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the bf16 / fp16 contraction timings")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -203,6 +207,9 @@ def main():
                            "achieved_TFLOPs": round(ach, 3),
                            "frac_of_mfma_peak": round(ach / MFMA16_PEAK_TFLOPS, 4)}
         result["mixed_precision"] = mixed
+    if not args.no_serving:
+        from paper_1609_05722_amd.serving import serving_report
+        result["serving"] = serving_report(prior, args.serving_requests, (0.9,), "bf16")
     if not args.no_cpu:
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
         result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)

@@ -157,6 +157,52 @@ fe_status fe_binned_workspace_size(const fe_ctx *ctx, const fe_job *jobs, int32_
 fe_status fe_denoise_binned(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
                             void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ---- continuous-batching server -----------------------------------------
+ * A worker thread admits submitted jobs in arrival order as device memory
+ * (a budget allocated once at create) frees up, keeps each admitted job's
+ * state resident, and runs ticks: every tick advances every resident job by
+ * up to iters_per_tick iterations in shared launches (fe_advance), starts
+ * newly admitted jobs (fe_begin) and finishes completed ones (fe_end).
+ * Results are bitwise those of fe_denoise on the job alone.  The client
+ * owns each job's counts and output buffers until its completion is polled. */
+typedef struct fe_server fe_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device memory for resident job states        */
+    int32_t iters_per_tick;   /* iterations per resident job per tick, >= 1   */
+    int32_t max_active;       /* most jobs resident at once, >= 1             */
+    int32_t ticks_in_flight;  /* ticks enqueued ahead of the device, 1..64    */
+} fe_server_config;
+
+typedef struct {
+    uint64_t tag;       /* the client's tag from fe_server_submit            */
+    int32_t status;     /* FE_OK                                             */
+    int32_t iterations;
+    double t_submit;    /* seconds since server creation (host clock)        */
+    double t_admit;     /* when its state became resident                    */
+    double t_done;      /* when the tick that finished it completed (device  */
+                        /* event, on the same time base)                     */
+} fe_completion;
+
+/* Create a server on the context's device; hip_stream NULL: its own stream.
+ * Allocates the budget and the tick workspaces once. */
+fe_status fe_server_create(const fe_ctx *ctx, const fe_server_config *cfg,
+                           void *hip_stream, fe_server **out);
+/* Queue one job (thread-safe, returns at once).  FE_ERR_INVALID if the job
+ * is malformed or its state can never fit the budget. */
+fe_status fe_server_submit(fe_server *srv, const fe_job *job, uint64_t tag);
+/* Move up to max completions to out (*n of them), waiting up to wait_ms
+ * for the first one. */
+fe_status fe_server_poll(fe_server *srv, fe_completion *out, int32_t max,
+                         int32_t *n, int32_t wait_ms);
+/* Jobs queued and resident now, and the server clock (seconds). */
+fe_status fe_server_load(fe_server *srv, int32_t *pending, int32_t *active,
+                         double *now);
+/* Finish every submitted job, then release the server (NULL allowed). */
+void fe_server_destroy(fe_server *srv);
+/* Message for the last non-OK status of a server call on this thread. */
+const char *fe_server_last_error(void);
+
 /* Workspace bytes fe_energy_grad needs for an H x W image. */
 fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,
                                         int32_t width, size_t *bytes);

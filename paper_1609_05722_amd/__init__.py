@@ -29,7 +29,8 @@ EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
            "fe_state_bytes", "fe_begin", "fe_advance_workspace_size", "fe_advance",
            "fe_end", "fe_binned_workspace_size", "fe_denoise_binned",
            "fe_energy_grad_workspace_size", "fe_energy_grad",
-           "fe_last_error")
+           "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_load",
+           "fe_server_destroy", "fe_server_last_error", "fe_last_error")
 
 
 class FeError(RuntimeError):

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfe.so")
-SOURCES = ["fe_runtime.cpp", "kernels_pointwise.hip", "kernels_direct.hip",
-           "kernels_fused.hip"]
+SOURCES = ["fe_runtime.cpp", "fe_server.cpp", "kernels_pointwise.hip",
+           "kernels_direct.hip", "kernels_fused.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -52,7 +52,8 @@ def build(verbose=False, jobs=4):
             print("\n".join(lines))
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o",
+           LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,100 @@
+// Host-only checks of the serving scheduler (admission by memory budget,
+// arrival order, per-tick iteration counts, deferred release).  Built with
+// g++ by tests/test_sched_cpu.py; prints "OK" and exits 0 on success.
+#include <cstdio>
+#include <cstdlib>
+
+#include "fe_sched.h"
+
+#define CHECK(c)                                                        \
+    do {                                                                \
+        if (!(c)) {                                                     \
+            std::printf("FAIL %s:%d %s\n", __FILE__, __LINE__, #c);    \
+            std::exit(1);                                               \
+        }                                                               \
+    } while (0)
+
+static void arena_tests()
+{
+    fe::Arena a(10 * 256);
+    size_t o1, o2, o3, o4;
+    CHECK(a.alloc(300, &o1) && o1 == 0);        // rounds up to 512
+    CHECK(a.alloc(256, &o2) && o2 == 512);
+    CHECK(a.alloc(1000, &o3) && o3 == 768);     // 1024 bytes
+    CHECK(a.used() == 512 + 256 + 1024);
+    CHECK(!a.alloc(1024, &o4));                 // only 768 left
+    a.release(o2, 256);
+    CHECK(a.largest_free() == 768);
+    a.release(o1, 300);                         // merges with the freed 256
+    CHECK(a.largest_free() == 768);
+    CHECK(a.alloc(768, &o4) && o4 == 0);        // first fit at the merged hole
+    a.release(o4, 768);
+    a.release(o3, 1000);
+    CHECK(a.used() == 0 && a.largest_free() == 10 * 256);
+}
+
+static void scheduler_tests()
+{
+    // budget for two 1 KiB jobs
+    fe::Scheduler s(2048, 10, 100);
+    CHECK(s.fits_ever(2048) && !s.fits_ever(2049));
+    const uint64_t a = s.submit(1024, 25, 0.0);
+    const uint64_t b = s.submit(1024, 10, 0.1);
+    const uint64_t c = s.submit(512, 5, 0.2);   // must wait behind a and b
+    fe::TickPlan t = s.plan(1.0);
+    CHECK(t.admitted.size() == 2 && t.admitted[0] == a && t.admitted[1] == b);
+    CHECK(t.active.size() == 2 && t.count[0] == 10 && t.count[1] == 10);
+    CHECK(t.done_before[0] == 0 && t.done_before[1] == 0);
+    CHECK(t.finishing.size() == 1 && t.finishing[0] == b);
+    CHECK(s.pending() == 1 && s.active() == 1 && s.retiring() == 1);
+    // b's memory is not reusable until its tick completed
+    t = s.plan(2.0);
+    CHECK(t.admitted.empty() && t.active.size() == 1 && t.count[0] == 10);
+    CHECK(t.done_before[0] == 10 && t.finishing.empty());
+    s.retire({b});
+    t = s.plan(3.0);
+    CHECK(t.admitted.size() == 1 && t.admitted[0] == c);
+    CHECK(t.active.size() == 2 && t.count[0] == 5 && t.count[1] == 5);
+    CHECK(t.finishing.size() == 2);
+    const fe::SchedJob *jc = s.find(c);
+    CHECK(jc && jc->t_admit == 3.0 && jc->t_submit == 0.2);
+    s.retire({a, c});
+    CHECK(s.active() == 0 && s.pending() == 0 && s.arena().used() == 0);
+}
+
+static void order_and_caps()
+{
+    // a large head blocks smaller later jobs (arrival order is kept)
+    fe::Scheduler s(4096, 7, 100);
+    const uint64_t small1 = s.submit(1024, 7, 0);
+    const uint64_t big = s.submit(4096, 7, 0);
+    const uint64_t small2 = s.submit(1024, 7, 0);
+    fe::TickPlan t = s.plan(0);
+    CHECK(t.admitted.size() == 1 && t.admitted[0] == small1);
+    s.retire(t.finishing);
+    t = s.plan(0);
+    CHECK(t.admitted.size() == 1 && t.admitted[0] == big);
+    s.retire(t.finishing);
+    t = s.plan(0);
+    CHECK(t.admitted.size() == 1 && t.admitted[0] == small2);
+    // the active cap
+    fe::Scheduler s2(1 << 20, 3, 2);
+    for (int i = 0; i < 5; ++i) s2.submit(1024, 9, 0);
+    t = s2.plan(0);
+    CHECK(t.admitted.size() == 2 && s2.pending() == 3);
+    // zero-iteration jobs are admitted and finish in the same tick
+    fe::Scheduler s3(4096, 3, 10);
+    const uint64_t z = s3.submit(256, 0, 0);
+    t = s3.plan(0);
+    CHECK(t.admitted.size() == 1 && t.count[0] == 0 && t.finishing.size() == 1 &&
+          t.finishing[0] == z);
+}
+
+int main()
+{
+    arena_tests();
+    scheduler_tests();
+    order_and_caps();
+    std::printf("OK\n");
+    return 0;
+}

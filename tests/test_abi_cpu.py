@@ -95,3 +95,16 @@ def test_stepping_calls_validate_before_device_work(lib):
     assert lib.fe_begin(None, None, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_advance(None, None, None, None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_end(None, None, None, None, 0, None) == fe.FE_ERR_INVALID
+
+
+def test_server_calls_validate_before_device_work(lib):
+    import paper_1609_05722_amd as fe
+    from paper_1609_05722_amd import serving
+    serving._bind()
+    h = ctypes.c_void_p()
+    cfg = serving._Cfg(1 << 20, 10, 4, 2)
+    assert lib.fe_server_create(None, ctypes.byref(cfg), None, ctypes.byref(h)) == fe.FE_ERR_INVALID
+    assert lib.fe_server_submit(None, None, 0) == fe.FE_ERR_INVALID
+    n = ctypes.c_int32()
+    assert lib.fe_server_poll(None, None, 0, ctypes.byref(n), 0) == fe.FE_ERR_INVALID
+    lib.fe_server_destroy(None)
