@@ -375,17 +375,19 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
     // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
-    // block column xr + R; hoff: H offset of (a, xr); valid: task exists.
+    // block column xr + R; hoff: H offset of (a, xr); xrr: xr, or a value
+    // that never lands in the row when the task does not exist (its loads
+    // then read a harmless in-range address and its store is skipped).
     int sbase[G::ROUNDS], hoff[G::ROUNDS], xrr[G::ROUNDS];
 #pragma unroll
     for (int rr = 0; rr < G::ROUNDS; ++rr) {
         const int task = rr * 64 + lane;
-        const int a = task / G::XSPAN;
-        const int xr = task - a * G::XSPAN - R;
         const bool ok = task < G::TASKS;
+        const int a = ok ? task / G::XSPAN : 0;
+        const int xr = ok ? task - a * G::XSPAN - R : 0;
         sbase[rr] = (a * M) * G::SW + G::SPAD + xr + R;
         hoff[rr] = a * kQW + xr;
-        xrr[rr] = ok ? xr : -1000;   // never a valid column when the task is absent
+        xrr[rr] = ok ? xr : -1000;
     }
     Math mth;
     mth.load(t0, t1, t2, t3, lane);
@@ -427,18 +429,28 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     //   H[a][16k + xr] (+)= sum_b C[xr + R - b][(a, b)]; the first block to
     //   reach a column writes it, the next one adds.
     auto collapse = [&](float *Hs, int k) {
+        // all loads first (no branch between them), then sums and stores
+        float v[G::ROUNDS][M], old[G::ROUNDS];
+        int hidx[G::ROUNDS];
+        bool st[G::ROUNDS], add[G::ROUNDS];
 #pragma unroll
         for (int rr = 0; rr < G::ROUNDS; ++rr) {
             const int xr = xrr[rr];
             const int x = 16 * k + xr;
-            if (x >= 0 && x < kQW) {           // false for absent tasks
-                const float *sp = Sw + sbase[rr];
-                float acc = sp[0];
+            st[rr] = x >= 0 && x < kQW;
+            add[rr] = k > 0 && xr < R;
+            hidx[rr] = st[rr] ? hoff[rr] + 16 * k : 0;
+            const float *sp = Sw + sbase[rr];
 #pragma unroll
-                for (int b = 1; b < M; ++b) acc += sp[b * (G::SW - 1)];
-                float *h = Hs + hoff[rr] + 16 * k;
-                *h = (k > 0 && xr < R) ? *h + acc : acc;
-            }
+            for (int b = 0; b < M; ++b) v[rr][b] = sp[b * (G::SW - 1)];
+            old[rr] = Hs[hidx[rr]];
+        }
+#pragma unroll
+        for (int rr = 0; rr < G::ROUNDS; ++rr) {
+            float acc = v[rr][0];
+#pragma unroll
+            for (int b = 1; b < M; ++b) acc += v[rr][b];
+            if (st[rr]) Hs[hidx[rr]] = add[rr] ? old[rr] + acc : acc;
         }
     };
     // ---- output rows: g = sum over ghosts and a of H; iPiano update --------
@@ -457,32 +469,43 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         if (orow < 0 || orow >= ty) return;    // uniform over the wave
         const int y = y0 + orow;
         const int x = x0 + (lane < tx ? lane : tx - 1);
-        // the output row and, at the top or bottom border, its ghost rows
-        int rows[3], nr = 0;
-        if (y < R) rows[nr++] = -1 - y;
-        rows[nr++] = y;
-        if (y >= H - R) rows[nr++] = 2 * H - 1 - y;
         // the column and, at the left or right border, its ghost columns
         // (both when W < 2R)
         const int hx = x - (x0 - R);
         const bool gl = x < R, gr = x >= W - R;
         const int hgl = gl ? (-1 - x) - (x0 - R) : hx;
         const int hgr = gr ? (2 * W - 1 - x) - (x0 - R) : hx;
-        float gsum = 0.0f;
-        for (int ir = 0; ir < nr; ++ir) {
+        // sum over a of H[row - a + R][a] for one extended row; every load
+        // is issued before the first add (rows off the image weigh zero)
+        auto row_sum = [&](int row) {
+            float vh[M], vl[M], vr[M];
+            bool ok[M];
 #pragma unroll
             for (int a = 0; a < M; ++a) {
-                const int qyy = rows[ir] - a + R;
-                if (qyy < 0 || qyy >= H) continue;     // uniform
-                int q = qyy - (y0 - R);
+                const int qyy = row - a + R;
+                ok[a] = qyy >= 0 && qyy < H;
+                int q = ok[a] ? qyy - (y0 - R) : 0;
                 q = q >= G::HR ? q % G::HR : q;
                 const float *h = Hr + (size_t)q * M * kQW + a * kQW;
-                const float vl = h[hgl], vr = h[hgr];
-                gsum += h[hx];
-                gsum += gl ? vl : 0.0f;
-                gsum += gr ? vr : 0.0f;
+                vh[a] = h[hx];
+                vl[a] = h[hgl];
+                vr[a] = h[hgr];
             }
-        }
+            float sum = 0.0f;
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                float t = vh[a];
+                t += gl ? vl[a] : 0.0f;
+                t += gr ? vr[a] : 0.0f;
+                sum += ok[a] ? t : 0.0f;
+            }
+            return sum;
+        };
+        // the output row and, at the top or bottom border, its ghost rows
+        float gsum = 0.0f;
+        if (y < R) gsum += row_sum(-1 - y);
+        gsum += row_sum(y);
+        if (y >= H - R) gsum += row_sum(2 * H - 1 - y);
         if (lane >= tx) return;
         const float uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
         const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
