@@ -46,7 +46,7 @@ bool fused_supported(int m, int nf);
 hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf,
                         FusedBank *out);
 void fused_release(FusedBank *b);
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan);
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw);
 size_t fused_table_bytes(int n);
 // Enqueues the job table and max(count) step launches per precision group;
 // job i is advanced by items[i].count iterations.

@@ -64,8 +64,9 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // HBM as well.
 typedef __attribute__((address_space(1))) float gfloat;
 
-constexpr int kWaves = 8;             // waves per workgroup
-constexpr int kThreads = 64 * kWaves; // 512
+// Waves per workgroup: 8 for FP32 (its registers allow two waves per
+// SIMD), 12 for BF16/FP16 (three per SIMD, to hide more LDS latency).
+constexpr int kWavesF32 = 8, kWavesP16 = 12;
 constexpr int kQB = 4;                // 16-pixel blocks per q-row
 constexpr int kQW = 16 * kQB;         // q-row width (pixels)
 
@@ -94,19 +95,26 @@ struct Geo {
     static constexpr int SROWS = (16 * NTB > T) ? 16 * NTB : T;  // scratch rows = taps
     static constexpr int SPAD = 8;                    // zero columns left of a block
     static constexpr int SW = 36;                     // scratch row stride (floats)
-    static constexpr int HR = 2 * kWaves + 2 * R;     // H ring slots (q-rows)
     static constexpr int XSPAN = 16 + 2 * R;          // columns one block reaches
     static constexpr int TASKS = M * XSPAN;           // (a, x) collapse tasks per block
     static constexpr int ROUNDS = (TASKS + 63) / 64;
     static constexpr int LAST_ROW = T - 1;            // scratch row of the last tap
 };
 
-template <int M>
+// H ring slots: with one barrier per pipeline step the rows being finished
+// (2R + NW q-rows) and the NW rows being written coexist; with two barriers
+// per step they do not.
+template <int M, int NW, bool TWO>
+struct Ring {
+    static constexpr int HR = TWO ? NW + (M - 1) : 2 * NW + (M - 1);
+};
+
+template <int M, int NW, bool TWO>
 size_t lds_bytes(int ty_max)
 {
     using G = Geo<M>;
-    return sizeof(float) * ((size_t)(ty_max + 4 * G::R) * G::US +
-                            (size_t)kWaves * G::SROWS * G::SW + (size_t)G::HR * M * kQW);
+    return sizeof(float) * ((size_t)(ty_max + 4 * G::R) * G::US + (size_t)NW * G::SROWS * G::SW +
+                            (size_t)Ring<M, NW, TWO>::HR * M * kQW);
 }
 
 __device__ __forceinline__ int sym_clamp(int i, int n)
@@ -142,6 +150,8 @@ __device__ __forceinline__ void lds_barrier()
 template <int M, int NFB>
 struct MathF32 {
     using G = Geo<M>;
+    static constexpr int kNW = kWavesF32;
+    static constexpr bool kTwo = false;
     float afwd[G::KF][NFB];
     float badj[NFB][4][G::NTB];
     float lastf[NFB][4], lasta[NFB][4];
@@ -243,6 +253,8 @@ struct MathF32 {
 template <int M, int NFB, typename P>
 struct MathP16 {
     using G = Geo<M>;
+    static constexpr int kNW = kWavesP16;
+    static constexpr bool kTwo = true;
     typedef P vec8 __attribute__((ext_vector_type(8)));
     static constexpr int KS = (G::T + 31) / 32;    // forward k-steps
     static constexpr int KA = (NFB + 1) / 2;       // adjoint k-steps (32 filters)
@@ -333,7 +345,7 @@ struct MathP16 {
 };
 
 template <int M, typename Math>
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__(64 * Math::kNW)
 void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                        const void *__restrict__ t0, const void *__restrict__ t1,
                        const void *__restrict__ t2, const void *__restrict__ t3,
@@ -341,6 +353,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 {
     using G = Geo<M>;
     constexpr int R = G::R;
+    constexpr int NW = Math::kNW;
+    constexpr int HR = Ring<M, NW, Math::kTwo>::HR;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -369,8 +383,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
-    float *S = U + (size_t)(ty_max + 4 * R) * G::US;       // kWaves x SROWS x SW
-    float *Hr = S + (size_t)kWaves * G::SROWS * G::SW;     // HR x M x QW
+    float *S = U + (size_t)(ty_max + 4 * R) * G::US;       // NW x SROWS x SW
+    float *Hr = S + (size_t)NW * G::SROWS * G::SW;         // HR x M x QW
     float *Sw = S + (size_t)wave * G::SROWS * G::SW;
 
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
@@ -397,7 +411,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
     const int urows = ty + 4 * R;
-    for (int i = threadIdx.x; i < urows * G::UC; i += kThreads) {
+    for (int i = threadIdx.x; i < urows * G::UC; i += 64 * NW) {
         const int ur = i / G::UC, uc = i - ur * G::UC;
         const int yy = sym_clamp(y0 - 2 * R + ur, H);
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
@@ -406,7 +420,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     __syncthreads();
 
     const int nq = ty + 2 * R;                 // q-rows of the tile
-    const int nsteps = (nq + kWaves - 1) / kWaves;
+    const int nsteps = (nq + NW - 1) / NW;
 
     using Acc = typename Math::Acc;
     // ---- one 16-pixel block: forward bank (matrix cores) ------------------
@@ -457,7 +471,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // Inputs of the row a wave will finish are fetched one step ahead.
     float pf_up = 0.0f, pf_y = 0.0f;
     auto prefetch = [&](int st) {
-        const int orow = st * kWaves - 2 * R + wave;
+        const int orow = st * NW - 2 * R + wave;
         if (orow >= 0 && orow < ty && lane < tx) {
             const long pix = (long)(y0 + orow) * W + x0 + lane;
             pf_up = uprev[pix];
@@ -465,7 +479,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
     auto finalize = [&](int st) {
-        const int orow = st * kWaves - 2 * R + wave;
+        const int orow = st * NW - 2 * R + wave;
         if (orow < 0 || orow >= ty) return;    // uniform over the wave
         const int y = y0 + orow;
         const int x = x0 + (lane < tx ? lane : tx - 1);
@@ -485,7 +499,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 const int qyy = row - a + R;
                 ok[a] = qyy >= 0 && qyy < H;
                 int q = ok[a] ? qyy - (y0 - R) : 0;
-                q = q >= G::HR ? q % G::HR : q;
+                q = q >= HR ? q % HR : q;
                 const float *h = Hr + (size_t)q * M * kQW + a * kQW;
                 vh[a] = h[hx];
                 vl[a] = h[hgl];
@@ -512,37 +526,53 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         uprev[(long)y * W + x] = prox(ut, anscombe(pf_y), J.tl, J.data_term);
     };
 
-    // Step st: finish the output rows of step st - 1, then run q-row
-    // st * 8 + wave.  One barrier per step; the H ring holds 2 * 8 + 2R
-    // q-rows so the rows being finished and the rows being written never
-    // share a slot.
-    for (int st = 0; st <= nsteps; ++st) {
-        if (st > 0) finalize(st - 1);
-        if (st < nsteps) {
-            prefetch(st);
-            const int qr = st * kWaves + wave;
-            const int qy = y0 - R + qr;
-            if (qr < nq && qy >= 0 && qy < H) {
-                float *Hs = Hr + (size_t)(qr % G::HR) * M * kQW;
-                Acc acc;
-                // software pipeline: the collapse of block k - 1 (LDS, VALU)
-                // is issued next to the forward MFMAs of block k
-                forward(qr, 0, acc);
-                adjoint(0, acc);
+    auto qrow = [&](int st) {
+        const int qr = st * NW + wave;
+        const int qy = y0 - R + qr;
+        if (qr < nq && qy >= 0 && qy < H) {
+            float *Hs = Hr + (size_t)(qr % HR) * M * kQW;
+            Acc acc;
+            // software pipeline: the collapse of block k - 1 (LDS, VALU) is
+            // issued next to the forward MFMAs of block k
+            forward(qr, 0, acc);
+            adjoint(0, acc);
 #pragma unroll
-                for (int k = 1; k < kQB; ++k) {
-                    lds_order();
-                    forward(qr, k, acc);
-                    collapse(Hs, k - 1);
-                    lds_order();
-                    adjoint(k, acc);
-                }
+            for (int k = 1; k < kQB; ++k) {
                 lds_order();
-                collapse(Hs, kQB - 1);
+                forward(qr, k, acc);
+                collapse(Hs, k - 1);
                 lds_order();
+                adjoint(k, acc);
             }
+            lds_order();
+            collapse(Hs, kQB - 1);
+            lds_order();
         }
-        lds_barrier();
+    };
+
+    if constexpr (Math::kTwo) {
+        // Step st: q-row st * NW + wave, barrier, then the output rows whose
+        // q-rows are now complete, barrier (the ring needs NW + 2R slots).
+        for (int st = 0; st < nsteps; ++st) {
+            prefetch(st);
+            qrow(st);
+            lds_barrier();
+            finalize(st);
+            lds_barrier();
+        }
+    } else {
+        // Step st: finish the output rows of step st - 1, then run q-row
+        // st * NW + wave.  One barrier per step; the ring holds 2 NW + 2R
+        // q-rows so rows being finished and rows being written never share
+        // a slot.
+        for (int st = 0; st <= nsteps; ++st) {
+            if (st > 0) finalize(st - 1);
+            if (st < nsteps) {
+                prefetch(st);
+                qrow(st);
+            }
+            lds_barrier();
+        }
     }
 }
 
@@ -566,16 +596,17 @@ template <int M, typename Math>
 hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, int ntiles,
                        int iter, int ty_max, hipStream_t s)
 {
-    const size_t bytes = lds_bytes<M>(ty_max);
+    constexpr int NW = Math::kNW;
+    const size_t bytes = lds_bytes<M, NW, Math::kTwo>(ty_max);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes<M>(kMaxTileRows));
+                                           (int)lds_bytes<M, NW, Math::kTwo>(kMaxTileRows));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    fused_step_kernel<M, Math><<<ntiles, kThreads, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
+    fused_step_kernel<M, Math><<<ntiles, 64 * NW, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
                                                                tabs[2], tabs[3], iter, ty_max);
     return hipGetLastError();
 }
@@ -736,8 +767,8 @@ void fused_release(FusedBank *b)
 
 // Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
 // count is chosen to fill the chip: the smallest per-CU work over rounds of
-// 256 workgroups, each tile costing ceil((ty + 2r) / 8) pipeline steps.
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan)
+// 256 workgroups, each tile costing ceil((ty + 2r) / nw) pipeline steps.
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw)
 {
     const int R = (m - 1) / 2, TX = kQW - 2 * R;
     const int kCUs = 256;
@@ -752,7 +783,7 @@ void make_plan(int m, const AdvanceItem *items, int n, Plan *plan)
             const int nty = (items[i].job->height + ty - 1) / ty;
             tiles += (long)ntx * nty;
             const int th = (items[i].job->height + nty - 1) / nty;
-            steps = std::max(steps, (th + 2 * R + kWaves - 1) / kWaves);
+            steps = std::max(steps, (th + 2 * R + nw - 1) / nw);
         }
         const long rounds = (tiles + kCUs - 1) / kCUs;
         const double cost = (double)rounds * steps;
@@ -792,7 +823,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         if (grp.empty()) continue;
         const int gn = (int)grp.size();
         Plan plan;
-        make_plan(bank.m, grp.data(), gn, &plan);
+        make_plan(bank.m, grp.data(), gn, &plan, prec == FE_PREC_FP32 ? kWavesF32 : kWavesP16);
         JobDesc *dj = table + slot;
         slot += gn;
         int max_it = 0, base = 0;
