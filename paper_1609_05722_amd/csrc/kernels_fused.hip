@@ -92,6 +92,7 @@ struct Geo {
     static constexpr int TX = kQW - 2 * R;            // output columns per tile
     static constexpr int UC = kQW + 2 * R;            // u tile columns
     static constexpr int US = UC + 2;                 // u tile row stride (floats)
+    static constexpr int UROWS_EXTRA = 1;             // row read (at weight 0) by padded taps
     static constexpr int SROWS = (16 * NTB > T) ? 16 * NTB : T;  // scratch rows = taps
     static constexpr int SPAD = 8;                    // zero columns left of a block
     static constexpr int SW = 36;                     // scratch row stride (floats)
@@ -113,7 +114,8 @@ template <int M, int NW, bool TWO>
 size_t lds_bytes(int ty_max)
 {
     using G = Geo<M>;
-    return sizeof(float) * ((size_t)(ty_max + 4 * G::R) * G::US + (size_t)NW * G::SROWS * G::SW +
+    return sizeof(float) * ((size_t)(ty_max + 4 * G::R + G::UROWS_EXTRA) * G::US +
+                            (size_t)NW * G::SROWS * G::SW +
                             (size_t)Ring<M, NW, TWO>::HR * M * kQW);
 }
 
@@ -256,12 +258,17 @@ struct MathP16 {
     static constexpr int kNW = kWavesP16;
     static constexpr bool kTwo = true;
     typedef P vec8 __attribute__((ext_vector_type(8)));
-    static constexpr int KS = (G::T + 31) / 32;    // forward k-steps
+    // M = 7: k-step s covers tap rows 4s..4s+3, lane group g row 4s + g,
+    // element e column e (8 x 8 padded; row 7 and column 7 weigh zero), so
+    // a lane's 8 values are consecutive in the LDS tile.  Otherwise taps are
+    // packed densely, 32 per k-step.
+    static constexpr bool PAD = (M == 7);
+    static constexpr int KS = PAD ? 2 : (G::T + 31) / 32;    // forward k-steps
     static constexpr int KA = (NFB + 1) / 2;       // adjoint k-steps (32 filters)
     static constexpr int NTBP = (G::T + 15) / 16;  // adjoint tap blocks
     u32x4 afwd[KS][NFB];
     u32x4 badj[KA][NTBP];
-    int boff[KS][8];
+    int boff[KS][PAD ? 1 : 8];
     struct Acc {
         f32x4 z[NFB];
     };
@@ -279,13 +286,18 @@ struct MathP16 {
 #pragma unroll
             for (int nb = 0; nb < NTBP; ++nb) badj[s][nb] = adj_tab[(s * NTBP + nb) * 64 + lane];
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int s = 0; s < KS; ++s) {
+            if constexpr (PAD) {
+                boff[s][0] = (4 * s + g) * G::US + p;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int t = 32 * s + 8 * g + e;
-                // padded taps read tap 0 (finite; its weight is zero)
-                boff[s][e] = t < G::T ? (t / M) * G::US + (t % M) + p : p;
+                for (int e = 0; e < 8; ++e) {
+                    const int t = 32 * s + 8 * g + e;
+                    // padded taps read tap 0 (finite; its weight is zero)
+                    boff[s][e] = t < G::T ? (t / M) * G::US + (t % M) + p : p;
+                }
             }
+        }
     }
 
     __device__ __forceinline__ void forward(const float *Ub, Acc &a) const
@@ -295,8 +307,14 @@ struct MathP16 {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             vec8 b;
+            if constexpr (PAD) {
+                const float *q = Ub + boff[s][0];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) b[e] = (P)Ub[boff[s][e]];
+                for (int e = 0; e < 8; ++e) b[e] = (P)q[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[e] = (P)Ub[boff[s][e]];
+            }
 #pragma unroll
             for (int fb = 0; fb < NFB; ++fb)
                 a.z[fb] = mfma(__builtin_bit_cast(vec8, afwd[s][fb]), b, a.z[fb]);
@@ -383,7 +401,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
-    float *S = U + (size_t)(ty_max + 4 * R) * G::US;       // NW x SROWS x SW
+    float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // NW x SROWS x SW
     float *Hr = S + (size_t)NW * G::SROWS * G::SW;         // HR x M x QW
     float *Sw = S + (size_t)wave * G::SROWS * G::SW;
 
@@ -410,9 +428,11 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
 
     // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
-    const int urows = ty + 4 * R;
-    for (int i = threadIdx.x; i < urows * G::UC; i += 64 * NW) {
-        const int ur = i / G::UC, uc = i - ur * G::UC;
+    // (one more row and the two padding columns hold finite values that
+    // zero-weight taps of the padded BF16/FP16 layout may read)
+    const int urows = ty + 4 * R + G::UROWS_EXTRA;
+    for (int i = threadIdx.x; i < urows * G::US; i += 64 * NW) {
+        const int ur = i / G::US, uc = i - ur * G::US;
         const int yy = sym_clamp(y0 - 2 * R + ur, H);
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
         U[ur * G::US + uc] = ucur[(long)yy * W + xx];
@@ -699,14 +719,17 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
                 lasta[(fb * 4 + j) * 64 + l] = a2(f) * tap(f, T - 1);
             }
     // BF16 / FP16 operands (16x16x32 lane layout; see MathP16)
-    const int KS = (T + 31) / 32, KA = (NFB + 1) / 2, NTBP = (T + 15) / 16;
+    const int KS = m == 7 ? 2 : (T + 31) / 32, KA = (NFB + 1) / 2, NTBP = (T + 15) / 16;
     std::vector<float> pf((size_t)KS * NFB * 64 * 8), pa((size_t)KA * NTBP * 64 * 8);
     for (int s = 0; s < KS; ++s)
         for (int fb = 0; fb < NFB; ++fb)
             for (int l = 0; l < 64; ++l)
                 for (int e = 0; e < 8; ++e)
                     pf[((s * NFB + fb) * 64 + l) * 8 + e] =
-                        tap(fb * 16 + (l & 15), 32 * s + 8 * (l >> 4) + e);
+                        m == 7 ? ((4 * s + (l >> 4)) < 7 && e < 7
+                                      ? tap(fb * 16 + (l & 15), (4 * s + (l >> 4)) * 7 + e)
+                                      : 0.0f)
+                               : tap(fb * 16 + (l & 15), 32 * s + 8 * (l >> 4) + e);
     for (int s = 0; s < KA; ++s)
         for (int nb = 0; nb < NTBP; ++nb)
             for (int l = 0; l < 64; ++l)
