@@ -79,6 +79,115 @@ def cpu_baseline(args, k, a, job, tau, gamma):
                          k.shape[2])}
 
 
+def _noisy_counts(job):
+    return job.arrays()[1]
+
+
+def batch_inputs(jobs, workers=8):
+    """Noisy counts of the uneven batch, generated on `workers` host
+    processes (spawned: they never touch the GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_noisy_counts, jobs, chunksize=4))
+
+
+def batch_report(fe, torch, prior, args, tau, gamma, log=None):
+    """Uneven batch: 256 images with sides log-uniform on [128, 1024],
+    peaks {1, 2, 4, 8}, 200 iterations each, all in one launch per
+    iteration.  Forms timed on the same inputs: one eager fe_denoise call
+    (cost-model tile height), the same after fe_autotune, the tuned advance
+    replayed as a captured HIP graph (fe_begin + replay + fe_end), and one
+    fe_denoise call per image.  The graph form is the headline."""
+    from synth.workloads import batch_config
+    cfg = batch_config(n_images=args.batch_images, iterations=args.iterations)
+    jobs = cfg["jobs"]
+    t0 = time.perf_counter()
+    ys = batch_inputs(jobs)
+    gen_s = time.perf_counter() - t0
+    counts = [torch.from_numpy(y).cuda() for y in ys]
+    del ys
+    m, nf = cfg["m"], cfg["n_filters"]
+    px = sum(j.height * j.width for j in jobs)
+    px_it = sum(j.height * j.width * j.iterations for j in jobs)
+    its = args.iterations
+    stream = torch.cuda.current_stream()
+    res = {"workload": "%d images, sides log-uniform on [128, 1024], aspect [0.5, 2], "
+                       "peaks {1,2,4,8}, %d 7x7 filters, %d iterations"
+                       % (len(jobs), nf, its),
+           "pixels": px, "pixel_iterations": px_it, "input_generation_s": round(gen_s, 1)}
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def rate(ms):
+        return {"ms": round(ms, 3), "Mpixel_iter_per_s": round(px_it / (ms * 1e-3) / 1e6, 1),
+                "images_per_s": round(len(jobs) / (ms * 1e-3), 2)}
+
+    for prec in args.batch_precisions.split(","):
+        specs = [fe.JobSpec(c, j.lam, j.iterations, tau, gamma, data_term=j.data_term,
+                            peak=j.peak, precision=prec) for c, j in zip(counts, jobs)]
+        arr, keep = fe.make_jobs(specs)
+        n = len(specs)
+        ws = fe.alloc_workspace(fe.workspace_size(prior, arr, n), "cuda")
+        lib = fe.library()
+
+        def eager():
+            fe._check(lib.fe_denoise(prior.handle, arr, n, fe._ptr(ws), ws.numel(),
+                                     fe._stream_handle(stream)))
+
+        out = {}
+        eager()
+        out["eager_cost_model"] = rate(timed(eager, 1))
+        b = fe.Batch(prior, specs, stream=stream)
+        t0 = time.perf_counter()
+        b.autotune(4)
+        torch.cuda.synchronize()
+        out["autotune_s"] = round(time.perf_counter() - t0, 2)
+        out["eager_tuned"] = rate(timed(eager, 1))
+        b.begin()
+        b.capture([its] * n)
+
+        def graph_job():
+            b.begin()
+            b.replay()
+            b.end()
+
+        graph_job()
+        out["graph_tuned"] = rate(timed(graph_job, max(1, args.batch_reps)))
+        b.release_graph()
+        if prec == "fp32" and not args.no_single:
+            singles = []
+            for sp in specs:
+                a1, k1 = fe.make_jobs([sp])
+                w1 = fe.alloc_workspace(fe.workspace_size(prior, a1, 1), "cuda")
+                singles.append((a1, k1, w1))
+
+            def one_at_a_time():
+                for a1, _, w1 in singles:
+                    fe._check(lib.fe_denoise(prior.handle, a1, 1, fe._ptr(w1), w1.numel(),
+                                             fe._stream_handle(stream)))
+
+            out["one_image_per_call"] = rate(timed(one_at_a_time, 1))
+            del singles
+        ach = flops_per_px_it(m, nf) * px_it / (out["graph_tuned"]["ms"] * 1e-3) / 1e12
+        peak = FP32_PEAK_TFLOPS if prec == "fp32" else MFMA16_PEAK_TFLOPS
+        out["achieved_TFLOPs"] = round(ach, 3)
+        out["frac_of_peak"] = round(ach / peak, 4)
+        res[prec] = out
+        if log:
+            log(json.dumps({"batch_" + prec: out}))
+        del b, keep, ws
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +198,13 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch section (256 images under a HIP graph)")
+    ap.add_argument("--batch-images", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--batch-precisions", default="fp32,bf16")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the one-image-per-call form of the batch section")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests per serving run (the full serving workload "
                          "is python -m paper_1609_05722_amd.serving)")
@@ -207,6 +323,9 @@ def main():
                            "achieved_TFLOPs": round(ach, 3),
                            "frac_of_mfma_peak": round(ach / MFMA16_PEAK_TFLOPS, 4)}
         result["mixed_precision"] = mixed
+    if not args.no_batch:
+        result["batch"] = batch_report(fe, torch, prior, args, tau, gamma,
+                                       log=lambda t: print(t, file=sys.stderr, flush=True))
     if not args.no_serving:
         from paper_1609_05722_amd.serving import serving_report
         result["serving"] = serving_report(prior, args.serving_requests, (0.9,), "bf16")

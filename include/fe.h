@@ -141,6 +141,38 @@ fe_status fe_advance(const fe_ctx *ctx, const fe_job *jobs, float *const *states
 fe_status fe_end(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
                  const int32_t *done, int32_t n, void *hip_stream);
 
+/* ---- tile-height autotuning --------------------------------------------
+ * The step's tile width is fixed by its q-row width; its height is picked
+ * per batch by a cost model unless this table holds a measured value for
+ * the batch's signature (precision and multiset of image sizes).
+ * fe_autotune times up to six candidate heights per precision group on
+ * scratch copies of the jobs' states (allocated for the call and freed;
+ * the jobs' own buffers are only read), trial_iterations (even) each, and
+ * records the fastest.  Synchronises the stream.  The table is internally
+ * locked; it can be saved to and loaded from a text file (one "height key"
+ * line per entry, '#' comments; heights outside 8..128 are rejected with
+ * FE_ERR_INVALID).  The tile height never changes results: every output
+ * pixel is computed by the same arithmetic whichever tile holds it. */
+fe_status fe_autotune(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
+                      int32_t trial_iterations, void *hip_stream);
+fe_status fe_tuning_save(const fe_ctx *ctx, const char *path);
+fe_status fe_tuning_load(const fe_ctx *ctx, const char *path);
+
+/* ---- captured step sequence ---------------------------------------------
+ * Captures one fe_advance (the job table upload and every step launch) into
+ * a HIP graph.  Each fe_graph_launch applies count[i] iterations to job i
+ * again; counts must be even so that a replay finds u^n in the plane it was
+ * captured with.  States, counts buffers and the workspace are referenced,
+ * not copied: keep them alive and unmodified while the graph is used.  No
+ * memset nodes are captured. */
+typedef struct fe_graph fe_graph;
+fe_status fe_advance_graph_create(const fe_ctx *ctx, const fe_job *jobs,
+                                  float *const *states, const int32_t *done,
+                                  const int32_t *count, int32_t n,
+                                  void *workspace, size_t ws_bytes, fe_graph **out);
+fe_status fe_graph_launch(const fe_graph *graph, void *hip_stream);
+void fe_graph_destroy(fe_graph *graph);
+
 /* ---- binning variant (Section 4: 3 x 3 ones kernel, bilinear upscaling;
  * the data term follows the binned image's peak, eq. 3.7) ----------------
  * Each job's counts are summed over non-overlapping 3 x 3 blocks (the image

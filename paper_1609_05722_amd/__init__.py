@@ -30,7 +30,9 @@ EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
            "fe_end", "fe_binned_workspace_size", "fe_denoise_binned",
            "fe_energy_grad_workspace_size", "fe_energy_grad",
            "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_load",
-           "fe_server_destroy", "fe_server_last_error", "fe_last_error")
+           "fe_server_destroy", "fe_server_last_error", "fe_autotune", "fe_tuning_save",
+           "fe_tuning_load", "fe_advance_graph_create", "fe_graph_launch",
+           "fe_graph_destroy", "fe_last_error")
 
 
 class FeError(RuntimeError):
@@ -97,6 +99,19 @@ def library():
         lib.fe_binned_workspace_size.restype = i32
         lib.fe_denoise_binned.argtypes = [vp, ctypes.POINTER(_Job), i32, vp, sz, vp]
         lib.fe_denoise_binned.restype = i32
+        lib.fe_autotune.argtypes = [vp, ctypes.POINTER(_Job), i32, i32, vp]
+        lib.fe_autotune.restype = i32
+        lib.fe_tuning_save.argtypes = [vp, ctypes.c_char_p]
+        lib.fe_tuning_save.restype = i32
+        lib.fe_tuning_load.argtypes = [vp, ctypes.c_char_p]
+        lib.fe_tuning_load.restype = i32
+        lib.fe_advance_graph_create.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, pi, i32, vp,
+                                                sz, ctypes.POINTER(vp)]
+        lib.fe_advance_graph_create.restype = i32
+        lib.fe_graph_launch.argtypes = [vp, vp]
+        lib.fe_graph_launch.restype = i32
+        lib.fe_graph_destroy.argtypes = [vp]
+        lib.fe_graph_destroy.restype = None
         lib.fe_last_error.argtypes = []
         lib.fe_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -319,6 +334,31 @@ class Batch:
                                     _stream_handle(self.stream)))
         for i in range(self.n):
             self.done[i] += cnt[i]
+
+    def capture(self, counts):
+        """A HIP graph of one advance by counts (even) from the current
+        iteration counts; each replay() applies them again."""
+        cnt = (ctypes.c_int32 * max(1, self.n))(*[int(c) for c in counts])
+        h = ctypes.c_void_p()
+        _check(library().fe_advance_graph_create(self.prior.handle, self.arr, self._sp,
+                                                 self.done, cnt, self.n, _ptr(self.ws),
+                                                 self.ws.numel(), ctypes.byref(h)))
+        self._graph, self._graph_counts = h, list(counts)
+        return h
+
+    def replay(self):
+        _check(library().fe_graph_launch(self._graph, _stream_handle(self.stream)))
+        for i in range(self.n):
+            self.done[i] += self._graph_counts[i]
+
+    def release_graph(self):
+        if getattr(self, "_graph", None) is not None:
+            library().fe_graph_destroy(self._graph)
+            self._graph = None
+
+    def autotune(self, trial_iterations=4):
+        _check(library().fe_autotune(self.prior.handle, self.arr, self.n,
+                                     int(trial_iterations), _stream_handle(self.stream)))
 
     def end(self):
         _check(library().fe_end(self.prior.handle, self.arr, self._sp, self.done, self.n,

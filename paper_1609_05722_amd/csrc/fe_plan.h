@@ -6,6 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "fe.h"
@@ -13,6 +16,7 @@
 namespace fe {
 
 constexpr int kMaxTileRows = 128;  // largest tile height a plan may pick
+constexpr int kMinTileRows = 8;    // smallest tile height a plan or a tuning file may pick
 
 // Matrix-core operand tables of one filter bank (see kernels_fused.hip).
 struct FusedBank {
@@ -42,15 +46,45 @@ struct AdvanceItem {
     int done, count;
 };
 
+// Measured tile heights: batch signature (precision and job sizes) ->
+// tile height.  Filled by fe_autotune, consulted by every plan.
+struct TuneTable {
+    mutable std::mutex mu;
+    std::map<std::string, int> ty;
+    int lookup(const std::string &key) const
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = ty.find(key);
+        return it == ty.end() ? 0 : it->second;
+    }
+    void store(const std::string &key, int v)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        ty[key] = v;
+    }
+};
+
+// Signature of one precision group of a batch: precision and the multiset
+// of image sizes of the jobs that advance.
+std::string batch_key(int prec, const AdvanceItem *items, int n);
+// Tile heights worth measuring for a group, best cost-model estimate first.
+std::vector<int> tile_candidates(int m, const AdvanceItem *items, int n, int nw, int max_n);
+int waves_for(int prec);
+
 bool fused_supported(int m, int nf);
 hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf,
                         FusedBank *out);
 void fused_release(FusedBank *b);
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw);
+// forced_ty > 0 imposes the tile height; otherwise the cost model picks it.
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw, int forced_ty = 0);
 size_t fused_table_bytes(int n);
 // Enqueues the job table and max(count) step launches per precision group;
 // job i is advanced by items[i].count iterations.
+// tune: measured tile heights (may be NULL); only_prec >= 0 restricts the
+// launch to one precision group and forced_ty imposes its tile height
+// (used while tuning).
 hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
-                     hipStream_t s);
+                     hipStream_t s, const TuneTable *tune = nullptr, int only_prec = -1,
+                     int forced_ty = 0);
 
 }  // namespace fe

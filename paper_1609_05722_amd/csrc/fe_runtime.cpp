@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <fstream>
+#include <sstream>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +25,7 @@ struct fe_ctx {
     std::vector<float> taps, alpha;  // host copies
     fe::DeviceBank bank;
     fe::FusedBank fused;             // matrix-core operand tables
+    mutable fe::TuneTable tune;      // measured tile heights (internally locked)
 };
 
 namespace {
@@ -176,7 +179,7 @@ fe_status enqueue_advance(const fe_ctx *c, const fe_job *jobs, float *const *sta
 {
     std::vector<fe::AdvanceItem> items(n);
     for (int i = 0; i < n; ++i) items[i] = {&jobs[i], states[i], done[i], count[i]};
-    hipError_t e = fe::run_fused(c->fused, items.data(), n, table, s);
+    hipError_t e = fe::run_fused(c->fused, items.data(), n, table, s, &c->tune);
     if (e != hipSuccess) return hip_fail(e, "fused step");
     return FE_OK;
 }
@@ -442,6 +445,165 @@ fe_status fe_denoise_binned(const fe_ctx *c, const fe_job *jobs, int32_t n, void
         if (e != hipSuccess) return hip_fail(e, "upsample3");
     }
     return FE_OK;
+}
+
+// ---- autotuning of the tile height ---------------------------------------
+fe_status fe_autotune(const fe_ctx *c, const fe_job *jobs, int32_t n, int32_t trial_iterations,
+                      void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st != FE_OK || n == 0) return st;
+    if (trial_iterations < 2 || (trial_iterations & 1))
+        return fail(FE_ERR_INVALID, "trial_iterations must be even and >= 2");
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    // scratch states and job table, allocated for the measurement only
+    size_t total = align256(fe::fused_table_bytes(n));
+    std::vector<size_t> off(n);
+    for (int i = 0; i < n; ++i) {
+        off[i] = total;
+        total += align256(state_bytes(jobs[i].height, jobs[i].width));
+    }
+    char *buf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc((void **)&buf, total);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    std::vector<float *> states(n);
+    std::vector<fe::AdvanceItem> items(n);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        states[i] = (float *)(buf + off[i]);
+        items[i] = {&jobs[i], states[i], 0, trial_iterations};
+    }
+    if (e == hipSuccess && enqueue_begin(jobs, states.data(), n, s) != FE_OK) e = hipErrorUnknown;
+    for (int prec = FE_PREC_FP32; prec <= FE_PREC_FP16 && e == hipSuccess; ++prec) {
+        std::vector<fe::AdvanceItem> grp;
+        for (auto &it : items)
+            if (it.job->precision == prec) grp.push_back(it);
+        if (grp.empty()) continue;
+        const int gn = (int)grp.size();
+        const std::vector<int> cand =
+            fe::tile_candidates(c->m, grp.data(), gn, fe::waves_for(prec), 6);
+        int best_ty = 0;
+        float best_ms = 1e30f;
+        for (int ty : cand) {
+            // one untimed pass, then the timed one (even counts keep parity)
+            e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, ty);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, ty);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_ty = ty;
+            }
+        }
+        if (e == hipSuccess && best_ty > 0)
+            c->tune.store(fe::batch_key(prec, grp.data(), gn), best_ty);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    return FE_OK;
+}
+
+fe_status fe_tuning_save(const fe_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(FE_ERR_INVALID, "ctx and path must be non-NULL");
+    std::ofstream f(path);
+    if (!f) return fail(FE_ERR_INVALID, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(c->tune.mu);
+    f << "# fe tuning table: m=" << c->m << " n_filters=" << c->nf << "\n";
+    for (auto &kv : c->tune.ty) f << kv.second << " " << kv.first << "\n";
+    return f ? FE_OK : fail(FE_ERR_INVALID, "write to %s failed", path);
+}
+
+fe_status fe_tuning_load(const fe_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(FE_ERR_INVALID, "ctx and path must be non-NULL");
+    std::ifstream f(path);
+    if (!f) return fail(FE_ERR_INVALID, "cannot read %s", path);
+    std::string line;
+    int loaded = 0;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ls(line);
+        int ty = 0;
+        std::string key;
+        if (!(ls >> ty >> key) || ty < fe::kMinTileRows || ty > fe::kMaxTileRows)
+            return fail(FE_ERR_INVALID, "malformed tuning line: %s", line.c_str());
+        c->tune.store(key, ty);
+        ++loaded;
+    }
+    return FE_OK;
+}
+
+// ---- captured step sequence ---------------------------------------------
+struct fe_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+fe_status fe_advance_graph_create(const fe_ctx *c, const fe_job *jobs, float *const *states,
+                                  const int32_t *done, const int32_t *count, int32_t n,
+                                  void *workspace, size_t ws_bytes, fe_graph **out)
+{
+    if (!out) return fail(FE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    fe_status st = check_batch(c, jobs, n);
+    if (st == FE_OK) st = check_states(jobs, states, n);
+    if (st != FE_OK) return st;
+    if (n == 0 || !done || !count) return fail(FE_ERR_INVALID, "empty batch or NULL counts");
+    for (int i = 0; i < n; ++i)
+        if (done[i] < 0 || count[i] < 0 || (count[i] & 1))
+            return fail(FE_ERR_INVALID, "job %d: counts must be even and >= 0 so that "
+                                        "replays keep the state parity", i);
+    size_t need = 0;
+    fe_advance_workspace_size(c, n, &need);
+    st = check_workspace(workspace, ws_bytes, need);
+    if (st != FE_OK) return st;
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    fe_graph *gr = new (std::nothrow) fe_graph;
+    if (!gr) return fail(FE_ERR_NOMEM, "host allocation failed");
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_advance(c, jobs, states, done, count, n, workspace, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &gr->graph);
+        if (st != FE_OK) e = hipErrorUnknown;
+        else e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        fe_graph_destroy(gr);
+        return st != FE_OK ? st : hip_fail(e, "graph capture");
+    }
+    *out = gr;
+    return FE_OK;
+}
+
+fe_status fe_graph_launch(const fe_graph *gr, void *hip_stream)
+{
+    if (!gr || !gr->exec) return fail(FE_ERR_INVALID, "graph is NULL");
+    hipError_t e = hipGraphLaunch(gr->exec, (hipStream_t)hip_stream);
+    return e == hipSuccess ? FE_OK : hip_fail(e, "graph launch");
+}
+
+void fe_graph_destroy(fe_graph *gr)
+{
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
 }
 
 fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)

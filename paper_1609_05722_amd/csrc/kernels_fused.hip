@@ -44,6 +44,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -791,30 +792,76 @@ void fused_release(FusedBank *b)
 // Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
 // count is chosen to fill the chip: the smallest per-CU work over rounds of
 // 256 workgroups, each tile costing ceil((ty + 2r) / nw) pipeline steps.
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw)
+namespace {
+// Cost-model estimate of one tile height for a group (lower is better):
+// rounds of 256 workgroups times pipeline steps per tile.
+double plan_cost(int m, const AdvanceItem *items, int n, int nw, int ty)
 {
     const int R = (m - 1) / 2, TX = kQW - 2 * R;
     const int kCUs = 256;
-    double best = 1e300;
-    int best_ty = 8;
-    for (int ty = 8; ty <= kMaxTileRows; ty += 1) {
-        long tiles = 0;
-        int steps = 0;
-        for (int i = 0; i < n; ++i) {
-            if (items[i].count <= 0) continue;
-            const int ntx = (items[i].job->width + TX - 1) / TX;
-            const int nty = (items[i].job->height + ty - 1) / ty;
-            tiles += (long)ntx * nty;
-            const int th = (items[i].job->height + nty - 1) / nty;
-            steps = std::max(steps, (th + 2 * R + nw - 1) / nw);
-        }
-        const long rounds = (tiles + kCUs - 1) / kCUs;
-        const double cost = (double)rounds * steps;
-        if (cost < best - 1e-9) {
-            best = cost;
-            best_ty = ty;
+    long tiles = 0;
+    int steps = 0;
+    for (int i = 0; i < n; ++i) {
+        if (items[i].count <= 0) continue;
+        const int ntx = (items[i].job->width + TX - 1) / TX;
+        const int nty = (items[i].job->height + ty - 1) / ty;
+        tiles += (long)ntx * nty;
+        const int th = (items[i].job->height + nty - 1) / nty;
+        steps = std::max(steps, (th + 2 * R + nw - 1) / nw);
+    }
+    const long rounds = (tiles + kCUs - 1) / kCUs;
+    return (double)rounds * steps;
+}
+}  // namespace
+
+int waves_for(int prec) { return prec == FE_PREC_FP32 ? kWavesF32 : kWavesP16; }
+
+std::string batch_key(int prec, const AdvanceItem *items, int n)
+{
+    std::vector<std::pair<int, int>> sz;
+    for (int i = 0; i < n; ++i)
+        if (items[i].count > 0) sz.emplace_back(items[i].job->height, items[i].job->width);
+    std::sort(sz.begin(), sz.end());
+    std::string k = "p" + std::to_string(prec) + ":";
+    for (auto &hw : sz) k += std::to_string(hw.first) + "x" + std::to_string(hw.second) + ",";
+    return k;
+}
+
+std::vector<int> tile_candidates(int m, const AdvanceItem *items, int n, int nw, int max_n)
+{
+    std::vector<std::pair<double, int>> c;
+    for (int ty = kMinTileRows; ty <= kMaxTileRows; ++ty) c.emplace_back(plan_cost(m, items, n, nw, ty), ty);
+    std::stable_sort(c.begin(), c.end(),
+                     [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int> out;
+    for (auto &e : c) {
+        if ((int)out.size() >= max_n) break;
+        out.push_back(e.second);
+    }
+    return out;
+}
+
+// Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
+// count comes from the tuning table if measured, else from the cost model
+// (fewest rounds of 256 workgroups times pipeline steps per tile).
+void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw, int forced_ty)
+{
+    const int R = (m - 1) / 2, TX = kQW - 2 * R;
+    int best_ty = forced_ty;
+    if (best_ty <= 0) {
+        double best = 1e300;
+        best_ty = kMinTileRows;
+        for (int ty = kMinTileRows; ty <= kMaxTileRows; ++ty) {
+            const double cost = plan_cost(m, items, n, nw, ty);
+            if (cost < best - 1e-9) {
+                best = cost;
+                best_ty = ty;
+            }
         }
     }
+    best_ty = std::min(std::max(best_ty, kMinTileRows), kMaxTileRows);
     plan->tile_w = TX;
     plan->tile_h = best_ty;
     plan->njobs = n;
@@ -833,20 +880,23 @@ size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(J
 size_t fused_table_bytes(int n) { return (size_t)std::max(n, 1) * sizeof(JobDesc); }
 
 hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
-                     hipStream_t s)
+                     hipStream_t s, const TuneTable *tune, int only_prec, int forced_ty)
 {
     // Jobs run in groups of equal precision (one kernel per precision); each
     // group has its own slice of the job table and its own plan.
     JobDesc *table = (JobDesc *)plan_ws;
     int slot = 0;
     for (int prec = FE_PREC_FP32; prec <= FE_PREC_FP16; ++prec) {
+        if (only_prec >= 0 && prec != only_prec) continue;
         std::vector<AdvanceItem> grp;
         for (int i = 0; i < n; ++i)
             if (items[i].job->precision == prec && items[i].count > 0) grp.push_back(items[i]);
         if (grp.empty()) continue;
         const int gn = (int)grp.size();
         Plan plan;
-        make_plan(bank.m, grp.data(), gn, &plan, prec == FE_PREC_FP32 ? kWavesF32 : kWavesP16);
+        int ty = forced_ty;
+        if (ty <= 0 && tune) ty = tune->lookup(batch_key(prec, grp.data(), gn));
+        make_plan(bank.m, grp.data(), gn, &plan, waves_for(prec), ty);
         JobDesc *dj = table + slot;
         slot += gn;
         int max_it = 0, base = 0;

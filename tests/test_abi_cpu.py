@@ -108,3 +108,16 @@ def test_server_calls_validate_before_device_work(lib):
     n = ctypes.c_int32()
     assert lib.fe_server_poll(None, None, 0, ctypes.byref(n), 0) == fe.FE_ERR_INVALID
     lib.fe_server_destroy(None)
+
+
+def test_tuning_and_graph_calls_validate_before_device_work(lib):
+    import paper_1609_05722_amd as fe
+    assert lib.fe_autotune(None, None, 0, 4, None) == fe.FE_ERR_INVALID
+    assert lib.fe_tuning_save(None, b"/tmp/x") == fe.FE_ERR_INVALID
+    assert lib.fe_tuning_load(None, b"/tmp/x") == fe.FE_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.fe_advance_graph_create(None, None, None, None, None, 0, None, 0,
+                                       ctypes.byref(h)) == fe.FE_ERR_INVALID
+    assert h.value is None
+    assert lib.fe_graph_launch(None, None) == fe.FE_ERR_INVALID
+    lib.fe_graph_destroy(None)  # NULL-safe

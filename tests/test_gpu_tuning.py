@@ -1,0 +1,117 @@
+"""The tile-height autotuner and the captured step sequence (HIP graph),
+both through the C ABI.  Neither may change a result: tuned, forced and
+replayed runs are compared bitwise with plain eager runs."""
+import numpy as np
+import pytest
+
+from synth import noisy_pair
+from synth.workloads import prior_for, step_size_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def fe(torch):
+    import paper_1609_05722_amd as fe
+    fe.library()
+    return fe
+
+
+def _specs(fe, torch, shapes, iters=12):
+    tau, gamma = step_size_for(7, 48)
+    out = []
+    for i, (H, W, pk, prec) in enumerate(shapes):
+        _, y = noisy_pair(700 + i, 800 + i, H, W, pk)
+        out.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, iters, tau, gamma,
+                              data_term="auto", peak=pk, precision=prec,
+                              want_anscombe=True))
+    return out
+
+
+SHAPES = [(96, 130, 2.0, "fp32"), (64, 64, 8.0, "bf16"), (200, 70, 1.0, "fp16"),
+          (150, 150, 4.0, "fp32")]
+
+
+def _equal(torch, a, b):
+    for (x0, u0), (x1, u1) in zip(a, b):
+        assert torch.equal(u0, u1) and torch.equal(x0, x1)
+
+
+def test_graph_replays_match_eager(fe, torch):
+    k, a = prior_for(7, 48)
+    prior = fe.Prior(k, a)
+    specs = _specs(fe, torch, SHAPES)
+    print("graph replay: %d jobs" % len(specs), flush=True)
+    eager, g = fe.Batch(prior, specs), fe.Batch(prior, specs)
+    for b in (eager, g):
+        b.begin()
+        b.advance([3, 3, 3, 3])
+    counts = [4, 6, 0, 2]
+    g.capture(counts)
+    try:
+        for r in range(4):
+            eager.advance(counts)
+            g.replay()
+            # unrelated eager work and a synchronisation between replays
+            junk = torch.randn(1 << 20, device="cuda") * 2.0
+            torch.cuda.synchronize()
+            del junk
+            for se, sg in zip(eager.states, g.states):
+                assert torch.equal(se, sg), "replay %d" % r
+    finally:
+        g.release_graph()
+    _equal(torch, eager.end(), g.end())
+    torch.cuda.synchronize()
+
+
+def test_graph_rejects_odd_counts(fe, torch):
+    k, a = prior_for(7, 48)
+    prior = fe.Prior(k, a)
+    b = fe.Batch(prior, _specs(fe, torch, SHAPES[:2]))
+    b.begin()
+    with pytest.raises(fe.FeError):
+        b.capture([3, 2])
+    torch.cuda.synchronize()
+
+
+def test_autotune_and_forced_heights_are_bitwise(fe, torch, tmp_path):
+    k, a = prior_for(7, 48)
+    specs = _specs(fe, torch, SHAPES)
+    ref = fe.denoise_jobs(fe.Prior(k, a), specs)
+    torch.cuda.synchronize()
+    prior = fe.Prior(k, a)
+    fe.Batch(prior, specs).autotune(4)
+    _equal(torch, ref, fe.denoise_jobs(prior, specs))
+    path = tmp_path / "tune.txt"
+    fe._check(fe.library().fe_tuning_save(prior.handle, str(path).encode()))
+    lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    keys = sorted(ln.split()[1] for ln in lines)
+    # one entry per precision group of the batch, keyed by its image sizes
+    assert keys == ["p0:96x130,150x150,", "p1:64x64,", "p2:200x70,"], keys
+    for ty in (8, 13, 64, 128):
+        forced = tmp_path / ("forced%d.txt" % ty)
+        forced.write_text("".join("%d %s\n" % (ty, key) for key in keys))
+        p2 = fe.Prior(k, a)
+        fe._check(fe.library().fe_tuning_load(p2.handle, str(forced).encode()))
+        print("forced tile height %d" % ty, flush=True)
+        _equal(torch, ref, fe.denoise_jobs(p2, specs))
+    torch.cuda.synchronize()
+
+
+def test_tuning_file_errors(fe, torch, tmp_path):
+    k, a = prior_for(7, 48)
+    prior = fe.Prior(k, a)
+    lib = fe.library()
+    assert lib.fe_tuning_load(prior.handle, str(tmp_path / "missing").encode()) == fe.FE_ERR_INVALID
+    for bad in ("7 p0:64x64,\n", "129 p0:64x64,\n", "x p0:64x64,\n"):
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        assert lib.fe_tuning_load(prior.handle, str(f).encode()) == fe.FE_ERR_INVALID
