@@ -79,19 +79,6 @@ def cpu_baseline(args, k, a, job, tau, gamma):
                          k.shape[2])}
 
 
-def _noisy_counts(job):
-    return job.arrays()[1]
-
-
-def batch_inputs(jobs, workers=8):
-    """Noisy counts of the uneven batch, generated on `workers` host
-    processes (spawned: they never touch the GPU)."""
-    import concurrent.futures as cf
-    import multiprocessing as mp
-    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(_noisy_counts, jobs, chunksize=4))
-
-
 def batch_report(fe, torch, prior, args, tau, gamma, log=None):
     """Uneven batch: 256 images with sides log-uniform on [128, 1024],
     peaks {1, 2, 4, 8}, 200 iterations each, all in one launch per
@@ -99,11 +86,11 @@ def batch_report(fe, torch, prior, args, tau, gamma, log=None):
     (cost-model tile height), the same after fe_autotune, the tuned advance
     replayed as a captured HIP graph (fe_begin + replay + fe_end), and one
     fe_denoise call per image.  The graph form is the headline."""
-    from synth.workloads import batch_config
+    from synth.workloads import batch_config, job_counts
     cfg = batch_config(n_images=args.batch_images, iterations=args.iterations)
     jobs = cfg["jobs"]
     t0 = time.perf_counter()
-    ys = batch_inputs(jobs)
+    ys = job_counts(jobs)
     gen_s = time.perf_counter() - t0
     counts = [torch.from_numpy(y).cuda() for y in ys]
     del ys

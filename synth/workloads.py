@@ -141,3 +141,19 @@ def serving_stream(n_requests=10000, rate=1.0, params=None, lo=64, hi=2048,
         times.append(t)
         jobs.append(_job(h, w, peak, 100000 + j, 200000 + j, its, params))
     return np.array(times), jobs
+
+
+def _job_counts(job):
+    return job.arrays()[1]
+
+
+def job_counts(jobs, workers=8):
+    """Noisy counts of many jobs, generated on `workers` spawned host
+    processes (they never touch a GPU); same values as job.arrays()[1]."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = list(jobs)
+    if workers <= 1 or len(jobs) < 8:
+        return [_job_counts(j) for j in jobs]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_job_counts, jobs, chunksize=4))

@@ -16,7 +16,7 @@ from scipy.stats import poisson
 
 import brute
 import oracle
-from synth import make_prior
+from synth import make_prior, noisy_pair
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
 
@@ -404,3 +404,28 @@ def test_upsample3_keeps_constants_and_centres():
     xb = np.random.default_rng(2).uniform(0, 9, (4, 5))
     x = oracle.upsample3(xb, 12, 15)
     assert np.abs(x[1::3, 1::3] - xb / 9.0).max() < 1e-14
+
+
+def test_iterations_are_local():
+    """After N iterations u^N at a pixel depends only on v within 2 r N of
+    it (forward and adjoint reach r each): the oracle on a crop with that
+    margin (or reaching a true border) reproduces the full-image value.
+    The GPU test of very large images relies on this."""
+    from synth.workloads import prior_for, step_size_for
+    k, a = prior_for(5, 24)
+    tau, gamma = step_size_for(5, 24)
+    _, y = noisy_pair(5, 6, 90, 110, 3.0)
+    iters, r = 3, 2
+    uf, xf = oracle.denoise(y, k, a, 30.0, tau, gamma, iters, 2)
+    marg = 2 * r * iters + 1
+    for (py, px) in [(0, 0), (45, 55), (89, 3), (20, 109), (60, 30)]:
+        y0, y1 = max(0, py - marg), min(90, py + marg + 1)
+        x0, x1 = max(0, px - marg), min(110, px + marg + 1)
+        uc, xc = oracle.denoise(y[y0:y1, x0:x1], k, a, 30.0, tau, gamma, iters, 2)
+        assert abs(uc[py - y0, px - x0] - uf[py, px]) < 1e-12
+    # one pixel less of margin is not enough somewhere
+    py, px = 45, 55
+    m = marg - 2
+    uc, _ = oracle.denoise(y[py - m:py + m + 1, px - m:px + m + 1], k, a, 30.0, tau, gamma,
+                           iters, 2)
+    assert abs(uc[m, m] - uf[py, px]) > 1e-12
