@@ -141,17 +141,20 @@ fe_status fe_advance(const fe_ctx *ctx, const fe_job *jobs, float *const *states
 fe_status fe_end(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
                  const int32_t *done, int32_t n, void *hip_stream);
 
-/* ---- tile-height autotuning --------------------------------------------
- * The step's tile width is fixed by its q-row width; its height is picked
- * per batch by a cost model unless this table holds a measured value for
- * the batch's signature (precision and multiset of image sizes).
- * fe_autotune times up to six candidate heights per precision group on
- * scratch copies of the jobs' states (allocated for the call and freed;
- * the jobs' own buffers are only read), trial_iterations (even) each, and
- * records the fastest.  Synchronises the stream.  The table is internally
- * locked; it can be saved to and loaded from a text file (one "height key"
- * line per entry, '#' comments; heights outside 8..128 are rejected with
- * FE_ERR_INVALID).  The tile height never changes results: every output
+/* ---- tile-shape autotuning ----------------------------------------------
+ * The step's tile width is fixed by its q-row width; its height, and for
+ * FP32 the waves per workgroup (8: every operand in registers; 12: adjoint
+ * tables in LDS), are picked per batch by a cost model and a default unless
+ * this table holds a measured choice for the batch's signature (precision
+ * and multiset of image sizes).  fe_autotune times up to six candidate
+ * heights per wave count and precision group on scratch copies of the
+ * jobs' states (allocated for the call and freed; the jobs' own buffers are
+ * only read), trial_iterations (even) each, and records the fastest.
+ * Synchronises the stream.  The table is internally locked; it can be saved
+ * to and loaded from a text file (one "waves height key" line per entry,
+ * '#' comments; a wave count the precision is not built for, or a height
+ * outside 8..(the variant's LDS limit, at most 128), is rejected with
+ * FE_ERR_INVALID).  The tile shape never changes results: every output
  * pixel is computed by the same arithmetic whichever tile holds it. */
 fe_status fe_autotune(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
                       int32_t trial_iterations, void *hip_stream);

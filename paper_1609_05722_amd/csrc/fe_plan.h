@@ -30,9 +30,10 @@ struct FusedBank {
 };
 
 // How a batch is cut into workgroup tiles: every job's image is split into
-// a grid of ntx x nty nearly equal tiles of at most tile_w x tile_h pixels.
+// a grid of ntx x nty nearly equal tiles of at most tile_w x tile_h pixels,
+// each run by a workgroup of `waves` waves.
 struct Plan {
-    int tile_w = 0, tile_h = 0;
+    int tile_w = 0, tile_h = 0, waves = 0;
     int njobs = 0, ntiles = 0;
     std::vector<int> jobs_ntx, jobs_nty;
     size_t device_bytes() const;  // job table in the workspace
@@ -46,45 +47,59 @@ struct AdvanceItem {
     int done, count;
 };
 
-// Measured tile heights: batch signature (precision and job sizes) ->
-// tile height.  Filled by fe_autotune, consulted by every plan.
+// Workgroup shape of the step: waves per workgroup and tile height.
+struct TileChoice {
+    int waves = 0, ty = 0;   // 0: not chosen (default waves, cost-model height)
+};
+
+// Measured tile shapes: batch signature (precision and job sizes) -> waves
+// and tile height.  Filled by fe_autotune, consulted by every plan.
 struct TuneTable {
     mutable std::mutex mu;
-    std::map<std::string, int> ty;
-    int lookup(const std::string &key) const
+    std::map<std::string, TileChoice> tab;
+    TileChoice lookup(const std::string &key) const
     {
         std::lock_guard<std::mutex> lk(mu);
-        auto it = ty.find(key);
-        return it == ty.end() ? 0 : it->second;
+        auto it = tab.find(key);
+        return it == tab.end() ? TileChoice{} : it->second;
     }
-    void store(const std::string &key, int v)
+    void store(const std::string &key, TileChoice v)
     {
         std::lock_guard<std::mutex> lk(mu);
-        ty[key] = v;
+        tab[key] = v;
     }
 };
 
 // Signature of one precision group of a batch: precision and the multiset
 // of image sizes of the jobs that advance.
 std::string batch_key(int prec, const AdvanceItem *items, int n);
-// Tile heights worth measuring for a group, best cost-model estimate first.
-std::vector<int> tile_candidates(int m, const AdvanceItem *items, int n, int nw, int max_n);
-int waves_for(int prec);
+// Tile heights worth measuring for a group run with nw waves per
+// workgroup, best cost-model estimate first.
+std::vector<int> tile_candidates(const FusedBank &bank, int prec, const AdvanceItem *items,
+                                 int n, int nw, int max_n);
+// Waves per workgroup the step is built for: default_waves(prec) unless a
+// measured choice says otherwise; wave_options lists every variant.
+int default_waves(int prec);
+std::vector<int> wave_options(int prec);
+// Tallest tile the variant's LDS allows (0 if no such variant).
+int max_tile_rows(const FusedBank &bank, int prec, int nw);
 
 bool fused_supported(int m, int nf);
 hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf,
                         FusedBank *out);
 void fused_release(FusedBank *b);
-// forced_ty > 0 imposes the tile height; otherwise the cost model picks it.
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw, int forced_ty = 0);
+// forced_ty > 0 imposes the tile height (clamped to the variant's range);
+// otherwise the cost model picks it.
+void make_plan(const FusedBank &bank, int prec, const AdvanceItem *items, int n, Plan *plan,
+               int nw, int forced_ty = 0);
 size_t fused_table_bytes(int n);
 // Enqueues the job table and max(count) step launches per precision group;
 // job i is advanced by items[i].count iterations.
-// tune: measured tile heights (may be NULL); only_prec >= 0 restricts the
-// launch to one precision group and forced_ty imposes its tile height
-// (used while tuning).
+// tune: measured tile shapes (may be NULL); only_prec >= 0 restricts the
+// launch to one precision group and `forced` imposes its shape (used while
+// tuning).
 hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
                      hipStream_t s, const TuneTable *tune = nullptr, int only_prec = -1,
-                     int forced_ty = 0);
+                     TileChoice forced = TileChoice{});
 
 }  // namespace fe

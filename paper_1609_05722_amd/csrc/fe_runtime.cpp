@@ -483,27 +483,30 @@ fe_status fe_autotune(const fe_ctx *c, const fe_job *jobs, int32_t n, int32_t tr
             if (it.job->precision == prec) grp.push_back(it);
         if (grp.empty()) continue;
         const int gn = (int)grp.size();
-        const std::vector<int> cand =
-            fe::tile_candidates(c->m, grp.data(), gn, fe::waves_for(prec), 6);
-        int best_ty = 0;
+        fe::TileChoice best;
         float best_ms = 1e30f;
-        for (int ty : cand) {
-            // one untimed pass, then the timed one (even counts keep parity)
-            e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, ty);
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, ty);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_ty = ty;
+        for (int nw : fe::wave_options(prec)) {
+            const std::vector<int> cand = fe::tile_candidates(c->fused, prec, grp.data(), gn, nw, 6);
+            for (int ty : cand) {
+                const fe::TileChoice tc{nw, ty};
+                // one untimed pass, then the timed one (even counts keep parity)
+                e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, tc);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = fe::run_fused(c->fused, grp.data(), gn, buf, s, nullptr, prec, tc);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = tc;
+                }
             }
+            if (e != hipSuccess) break;
         }
-        if (e == hipSuccess && best_ty > 0)
-            c->tune.store(fe::batch_key(prec, grp.data(), gn), best_ty);
+        if (e == hipSuccess && best.ty > 0)
+            c->tune.store(fe::batch_key(prec, grp.data(), gn), best);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -519,8 +522,9 @@ fe_status fe_tuning_save(const fe_ctx *c, const char *path)
     std::ofstream f(path);
     if (!f) return fail(FE_ERR_INVALID, "cannot write %s", path);
     std::lock_guard<std::mutex> lk(c->tune.mu);
-    f << "# fe tuning table: m=" << c->m << " n_filters=" << c->nf << "\n";
-    for (auto &kv : c->tune.ty) f << kv.second << " " << kv.first << "\n";
+    f << "# fe tuning table: m=" << c->m << " n_filters=" << c->nf
+      << "; lines: waves tile_height key\n";
+    for (auto &kv : c->tune.tab) f << kv.second.waves << " " << kv.second.ty << " " << kv.first << "\n";
     return f ? FE_OK : fail(FE_ERR_INVALID, "write to %s failed", path);
 }
 
@@ -534,11 +538,17 @@ fe_status fe_tuning_load(const fe_ctx *c, const char *path)
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#') continue;
         std::istringstream ls(line);
-        int ty = 0;
+        int nw = 0, ty = 0;
         std::string key;
-        if (!(ls >> ty >> key) || ty < fe::kMinTileRows || ty > fe::kMaxTileRows)
+        if (!(ls >> nw >> ty >> key) || key.size() < 3 || key[0] != 'p')
             return fail(FE_ERR_INVALID, "malformed tuning line: %s", line.c_str());
-        c->tune.store(key, ty);
+        const int prec = key[1] - '0';
+        const int hi = (prec >= FE_PREC_FP32 && prec <= FE_PREC_FP16)
+                           ? fe::max_tile_rows(c->fused, prec, nw) : 0;
+        if (hi <= 0 || ty < fe::kMinTileRows || ty > hi)
+            return fail(FE_ERR_INVALID, "tuning line out of range (waves %d, height %d): %s",
+                        nw, ty, line.c_str());
+        c->tune.store(key, fe::TileChoice{nw, ty});
         ++loaded;
     }
     return FE_OK;

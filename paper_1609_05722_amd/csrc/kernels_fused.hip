@@ -64,10 +64,14 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // count against the LDS wait counter and would make every LDS wait wait for
 // HBM as well.
 typedef __attribute__((address_space(1))) float gfloat;
+// LDS quad: 16-byte reads through it compile to ds_read_b128.
+typedef __attribute__((address_space(3))) f32x4 lquad;
 
-// Waves per workgroup: 8 for FP32 (its registers allow two waves per
-// SIMD), 12 for BF16/FP16 (three per SIMD, to hide more LDS latency).
+// Waves per workgroup: FP32 is built for 8 (every operand in registers,
+// two waves per SIMD) and 12 (adjoint tables in LDS, three per SIMD);
+// BF16/FP16 for 12 (three per SIMD).
 constexpr int kWavesF32 = 8, kWavesP16 = 12;
+constexpr int kDefaultWavesF32 = 12;
 constexpr int kQB = 4;                // 16-pixel blocks per q-row
 constexpr int kQW = 16 * kQB;         // q-row width (pixels)
 
@@ -111,13 +115,34 @@ struct Ring {
     static constexpr int HR = TWO ? NW + (M - 1) : 2 * NW + (M - 1);
 };
 
-template <int M, int NW, bool TWO>
+// LDS of one workgroup: the u tile, the per-wave tap scratch, the H ring
+// and the policy's operand tables (if it keeps any in LDS).
+constexpr int kLdsFloats = 160 * 1024 / 4;
+
+template <int M, typename Math>
+constexpr size_t lds_fixed_floats()
+{
+    using G = Geo<M>;
+    return (size_t)Math::kNW * G::SROWS * G::SW +
+           (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * kQW + Math::kTabFloats;
+}
+
+template <int M, typename Math>
 size_t lds_bytes(int ty_max)
 {
     using G = Geo<M>;
     return sizeof(float) * ((size_t)(ty_max + 4 * G::R + G::UROWS_EXTRA) * G::US +
-                            (size_t)NW * G::SROWS * G::SW +
-                            (size_t)Ring<M, NW, TWO>::HR * M * kQW);
+                            lds_fixed_floats<M, Math>());
+}
+
+// Tallest tile whose workgroup fits the LDS.
+template <int M, typename Math>
+constexpr int rows_limit()
+{
+    using G = Geo<M>;
+    const long rows = ((long)kLdsFloats - (long)lds_fixed_floats<M, Math>()) / G::US -
+                      (4 * G::R + G::UROWS_EXTRA);
+    return rows < kMaxTileRows ? (int)rows : kMaxTileRows;
 }
 
 __device__ __forceinline__ int sym_clamp(int i, int n)
@@ -150,22 +175,53 @@ __device__ __forceinline__ void lds_barrier()
 //   t1 adjoint B   [NFB][4][NTB][64]  B[k: filter 16fb + 4(l/16) + j][tap 16nb + l%16] * 2 alpha
 //   t2 last tap    [NFB][4][64]       tap m^2-1 of filter 16fb + 4(l/16) + j
 //   t3 last tap    [NFB][4][64]       the same times 2 alpha
-template <int M, int NFB>
+// LDS = false: 8 waves per workgroup, every operand in registers (two waves
+// per SIMD), one barrier per pipeline step.  LDS = true: 12 waves (three per
+// SIMD); the adjoint operands and both last-tap tables live in LDS, one row
+// of 16-byte aligned floats per lane (row strides of 4 mod 8 floats keep the
+// 16-byte reads of eight consecutive lanes on distinct banks); two barriers
+// per step.
+constexpr int odd_quads(int n) { return ((n + 3) / 4) % 2 ? (n + 3) / 4 * 4 : (n + 3) / 4 * 4 + 4; }
+
+template <int M, int NFB, bool LDS>
 struct MathF32 {
     using G = Geo<M>;
-    static constexpr int kNW = kWavesF32;
-    static constexpr bool kTwo = false;
+    static constexpr int kNW = LDS ? 12 : kWavesF32;
+    static constexpr bool kTwo = LDS;
+    static constexpr int NA = NFB * 4 * G::NTB;          // adjoint operands per lane
+    static constexpr int SA = odd_quads(NA), SL = odd_quads(NFB * 4);
+    static constexpr int kTabFloats = LDS ? 64 * (SA + 2 * SL) : 0;
+    static constexpr int RB = LDS ? 1 : NFB;             // register-resident copies
     float afwd[G::KF][NFB];
-    float badj[NFB][4][G::NTB];
-    float lastf[NFB][4], lasta[NFB][4];
+    float badj[RB][LDS ? 1 : 4][LDS ? 1 : G::NTB];
+    float lastf[RB][LDS ? 1 : 4], lasta[RB][LDS ? 1 : 4];
+    const float *tabA, *tabF, *tabL;                     // this lane's LDS rows
     int boff[G::KF], loff, perm16, perm32;
     struct Acc {
         f32x4 z[NFB];
         float ul;
     };
 
+    // LDS copies of the adjoint and last-tap tables (all threads; the
+    // caller's barrier publishes them).
+    static __device__ void stage(float *tab, const void *t1, const void *t2, const void *t3,
+                                 int tid, int nthreads)
+    {
+        if constexpr (LDS) {
+            const float *adj = (const float *)t1, *lf = (const float *)t2,
+                        *la = (const float *)t3;
+            for (int i = tid; i < 64 * NA; i += nthreads)
+                tab[(i & 63) * SA + (i >> 6)] = adj[i];
+            float *tf = tab + 64 * SA, *tl = tf + 64 * SL;
+            for (int i = tid; i < 64 * NFB * 4; i += nthreads) {
+                tf[(i & 63) * SL + (i >> 6)] = lf[i];
+                tl[(i & 63) * SL + (i >> 6)] = la[i];
+            }
+        }
+    }
+
     __device__ void load(const void *t0, const void *t1, const void *t2, const void *t3,
-                         int lane)
+                         int lane, const float *tab)
     {
         const float *fwd_tab = (const float *)t0, *adj_tab = (const float *)t1;
         const float *lastf_tab = (const float *)t2, *lasta_tab = (const float *)t3;
@@ -174,20 +230,26 @@ struct MathF32 {
         for (int s = 0; s < G::KF; ++s)
 #pragma unroll
             for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
+        if constexpr (LDS) {
+            tabA = tab + lane * SA;
+            tabF = tab + 64 * SA + lane * SL;
+            tabL = tab + 64 * (SA + SL) + lane * SL;
+        } else {
 #pragma unroll
-        for (int fb = 0; fb < NFB; ++fb)
+            for (int fb = 0; fb < NFB; ++fb)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int nb = 0; nb < G::NTB; ++nb)
-                    badj[fb][j][nb] = adj_tab[((fb * 4 + j) * G::NTB + nb) * 64 + lane];
+                    for (int nb = 0; nb < G::NTB; ++nb)
+                        badj[fb][j][nb] = adj_tab[((fb * 4 + j) * G::NTB + nb) * 64 + lane];
 #pragma unroll
-        for (int fb = 0; fb < NFB; ++fb)
+            for (int fb = 0; fb < NFB; ++fb)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                lastf[fb][j] = lastf_tab[(fb * 4 + j) * 64 + lane];
-                lasta[fb][j] = lasta_tab[(fb * 4 + j) * 64 + lane];
-            }
+                for (int j = 0; j < 4; ++j) {
+                    lastf[fb][j] = lastf_tab[(fb * 4 + j) * 64 + lane];
+                    lasta[fb][j] = lasta_tab[(fb * 4 + j) * 64 + lane];
+                }
+        }
         // LDS offsets of the forward B operand: tap 4s + g at pixel p
 #pragma unroll
         for (int s = 0; s < G::KF; ++s) {
@@ -214,6 +276,43 @@ struct MathF32 {
         a.ul = Ub[loff];
     }
 
+    // LDS operands of filter block fb: the adjoint B values for (j, nb) as
+    // NTB 16-byte quads (element j * NTB + nb) and one quad of each last-tap
+    // table (element j).
+    struct Ops {
+        f32x4 a[LDS ? G::NTB : 1], f, l;
+    };
+    __device__ __forceinline__ void fetch(int fb, Ops &o) const
+    {
+        if constexpr (LDS) {
+            // one 16-byte LDS read per quad (volatile keeps each read whole)
+            const volatile lquad *A = (const volatile lquad *)tabA + fb * G::NTB;
+#pragma unroll
+            for (int q = 0; q < G::NTB; ++q) o.a[q] = A[q];
+            o.f = ((const volatile lquad *)tabF)[fb];
+            o.l = ((const volatile lquad *)tabL)[fb];
+        }
+    }
+    __device__ __forceinline__ float adj_op(const Ops &o, int fb, int j, int nb) const
+    {
+        if constexpr (LDS) {
+            const int i = j * G::NTB + nb;
+            return o.a[i >> 2][i & 3];
+        } else {
+            return badj[fb][j][nb];
+        }
+    }
+    __device__ __forceinline__ float last_f(const Ops &o, int fb, int j) const
+    {
+        if constexpr (LDS) return o.f[j];
+        else return lastf[fb][j];
+    }
+    __device__ __forceinline__ float last_a(const Ops &o, int fb, int j) const
+    {
+        if constexpr (LDS) return o.l[j];
+        else return lasta[fb][j];
+    }
+
     // Influence, adjoint, tap contributions C[px][tap] into the scratch.
     template <bool MASK>
     __device__ __forceinline__ void adjoint(const Acc &a, bool inside, int p, int g,
@@ -225,15 +324,18 @@ struct MathF32 {
         float part = 0.0f;
 #pragma unroll
         for (int fb = 0; fb < NFB; ++fb) {
+            Ops o;
+            fetch(fb, o);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float zz = fmaf(lastf[fb][j], a.ul, a.z[fb][j]);
+                const float zz = fmaf(last_f(o, fb, j), a.ul, a.z[fb][j]);
                 float phi = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
                 if (MASK) phi = inside ? phi : 0.0f;
 #pragma unroll
                 for (int nb = 0; nb < G::NTB; ++nb)
-                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, badj[fb][j][nb], c[nb], 0, 0, 0);
-                part = fmaf(lasta[fb][j], phi, part);
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, adj_op(o, fb, j, nb), c[nb],
+                                                                 0, 0, 0);
+                part = fmaf(last_a(o, fb, j), phi, part);
             }
         }
         part += __int_as_float(__builtin_amdgcn_ds_bpermute(perm16, __float_as_int(part)));
@@ -258,6 +360,7 @@ struct MathP16 {
     using G = Geo<M>;
     static constexpr int kNW = kWavesP16;
     static constexpr bool kTwo = true;
+    static constexpr int kTabFloats = 0;
     typedef P vec8 __attribute__((ext_vector_type(8)));
     // M = 7: k-step s covers tap rows 4s..4s+3, lane group g row 4s + g,
     // element e column e (8 x 8 padded; row 7 and column 7 weigh zero), so
@@ -274,7 +377,10 @@ struct MathP16 {
         f32x4 z[NFB];
     };
 
-    __device__ void load(const void *t0, const void *t1, const void *, const void *, int lane)
+    static __device__ void stage(float *, const void *, const void *, const void *, int, int) {}
+
+    __device__ void load(const void *t0, const void *t1, const void *, const void *, int lane,
+                         const float *)
     {
         const u32x4 *fwd_tab = (const u32x4 *)t0, *adj_tab = (const u32x4 *)t1;
         const int p = lane & 15, g = lane >> 4;
@@ -404,6 +510,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *U = lds;                                        // (ty_max + 4R) x US
     float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // NW x SROWS x SW
     float *Hr = S + (size_t)NW * G::SROWS * G::SW;         // HR x M x QW
+    float *Tab = Hr + (size_t)HR * M * kQW;                // the policy's tables
     float *Sw = S + (size_t)wave * G::SROWS * G::SW;
 
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
@@ -423,7 +530,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         xrr[rr] = ok ? xr : -1000;
     }
     Math mth;
-    mth.load(t0, t1, t2, t3, lane);
+    mth.load(t0, t1, t2, t3, lane, Tab);
 
     // ---- zero this wave's scratch (its pad columns stay zero) -------------
     for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
@@ -438,6 +545,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
         U[ur * G::US + uc] = ucur[(long)yy * W + xx];
     }
+    Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
     __syncthreads();
 
     const int nq = ty + 2 * R;                 // q-rows of the tile
@@ -618,12 +726,13 @@ hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, 
                        int iter, int ty_max, hipStream_t s)
 {
     constexpr int NW = Math::kNW;
-    const size_t bytes = lds_bytes<M, NW, Math::kTwo>(ty_max);
+    if (ty_max > rows_limit<M, Math>()) return hipErrorInvalidValue;
+    const size_t bytes = lds_bytes<M, Math>(ty_max);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes<M, NW, Math::kTwo>(kMaxTileRows));
+                                           (int)lds_bytes<M, Math>(rows_limit<M, Math>()));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -632,9 +741,14 @@ hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, 
     return hipGetLastError();
 }
 
+// The 12-wave FP32 variant is built where its registers fit three waves
+// per SIMD (168): 64 filters of 7 x 7 do not.
 template <int M, int NFB>
-hipError_t launch_prec(int prec, const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
-                       int iter, int ty_max, hipStream_t s)
+constexpr bool f32_lds_built() { return !(M == 7 && NFB == 4); }
+
+template <int M, int NFB>
+hipError_t launch_prec(int prec, int nw, const FusedBank &b, const JobDesc *jobs, int njobs,
+                       int ntiles, int iter, int ty_max, hipStream_t s)
 {
     if (prec == FE_PREC_BF16) {
         const void *t[4] = {b.bf_fwd, b.bf_adj, nullptr, nullptr};
@@ -645,13 +759,34 @@ hipError_t launch_prec(int prec, const FusedBank &b, const JobDesc *jobs, int nj
         return launch_step<M, MathP16<M, NFB, _Float16>>(t, jobs, njobs, ntiles, iter, ty_max, s);
     }
     const void *t[4] = {b.fwd, b.adj, b.lastf, b.lasta};
-    return launch_step<M, MathF32<M, NFB>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+    if (nw == 12) {
+        if constexpr (f32_lds_built<M, NFB>())
+            return launch_step<M, MathF32<M, NFB, true>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+        return hipErrorInvalidValue;
+    }
+    return launch_step<M, MathF32<M, NFB, false>>(t, jobs, njobs, ntiles, iter, ty_max, s);
 }
 
-hipError_t launch_any(int prec, const FusedBank &b, const JobDesc *jobs, int njobs, int ntiles,
-                      int iter, int ty_max, hipStream_t s)
+// Tallest tile of a variant (0 if the variant is not built).
+template <int M, int NFB>
+int rows_prec(int prec, int nw)
 {
-#define FE_STEP(MM, NB) return launch_prec<MM, NB>(prec, b, jobs, njobs, ntiles, iter, ty_max, s)
+    if (prec == FE_PREC_BF16)
+        return nw == kWavesP16 ? rows_limit<M, MathP16<M, NFB, __bf16>>() : 0;
+    if (prec == FE_PREC_FP16)
+        return nw == kWavesP16 ? rows_limit<M, MathP16<M, NFB, _Float16>>() : 0;
+    if (nw == 12) {
+        if constexpr (f32_lds_built<M, NFB>()) return rows_limit<M, MathF32<M, NFB, true>>();
+        return 0;
+    }
+    return nw == kWavesF32 ? rows_limit<M, MathF32<M, NFB, false>>() : 0;
+}
+
+hipError_t launch_any(int prec, int nw, const FusedBank &b, const JobDesc *jobs, int njobs,
+                      int ntiles, int iter, int ty_max, hipStream_t s)
+{
+#define FE_STEP(MM, NB) \
+    return launch_prec<MM, NB>(prec, nw, b, jobs, njobs, ntiles, iter, ty_max, s)
     switch (b.m * 10 + b.nfb) {
     case 31: FE_STEP(3, 1);
     case 32: FE_STEP(3, 2);
@@ -812,9 +947,53 @@ double plan_cost(int m, const AdvanceItem *items, int n, int nw, int ty)
     const long rounds = (tiles + kCUs - 1) / kCUs;
     return (double)rounds * steps;
 }
+
+int rows_any(int m, int nfb, int prec, int nw)
+{
+#define FE_ROWS(MM, NB) return rows_prec<MM, NB>(prec, nw)
+    switch (m * 10 + nfb) {
+    case 31: FE_ROWS(3, 1);
+    case 32: FE_ROWS(3, 2);
+    case 33: FE_ROWS(3, 3);
+    case 34: FE_ROWS(3, 4);
+    case 51: FE_ROWS(5, 1);
+    case 52: FE_ROWS(5, 2);
+    case 53: FE_ROWS(5, 3);
+    case 54: FE_ROWS(5, 4);
+    case 71: FE_ROWS(7, 1);
+    case 72: FE_ROWS(7, 2);
+    case 73: FE_ROWS(7, 3);
+    case 74: FE_ROWS(7, 4);
+    default: return 0;
+    }
+#undef FE_ROWS
+}
 }  // namespace
 
-int waves_for(int prec) { return prec == FE_PREC_FP32 ? kWavesF32 : kWavesP16; }
+// FP32: 12 waves with LDS-resident adjoint tables measured faster than 8
+// waves with every operand in registers; both remain for the autotuner.
+int default_waves(int prec) { return prec == FE_PREC_FP32 ? kDefaultWavesF32 : kWavesP16; }
+
+// The default when its variant exists for this bank, else the other one.
+int bank_default_waves(const FusedBank &bank, int prec)
+{
+    const int nw = default_waves(prec);
+    if (max_tile_rows(bank, prec, nw) > 0) return nw;
+    for (int w : wave_options(prec))
+        if (max_tile_rows(bank, prec, w) > 0) return w;
+    return nw;
+}
+
+std::vector<int> wave_options(int prec)
+{
+    if (prec == FE_PREC_FP32) return {kWavesF32, 12};
+    return {kWavesP16};
+}
+
+int max_tile_rows(const FusedBank &bank, int prec, int nw)
+{
+    return rows_any(bank.m, bank.nfb, prec, nw);
+}
 
 std::string batch_key(int prec, const AdvanceItem *items, int n)
 {
@@ -827,10 +1006,13 @@ std::string batch_key(int prec, const AdvanceItem *items, int n)
     return k;
 }
 
-std::vector<int> tile_candidates(int m, const AdvanceItem *items, int n, int nw, int max_n)
+std::vector<int> tile_candidates(const FusedBank &bank, int prec, const AdvanceItem *items,
+                                 int n, int nw, int max_n)
 {
+    const int hi = max_tile_rows(bank, prec, nw);
     std::vector<std::pair<double, int>> c;
-    for (int ty = kMinTileRows; ty <= kMaxTileRows; ++ty) c.emplace_back(plan_cost(m, items, n, nw, ty), ty);
+    for (int ty = kMinTileRows; ty <= hi; ++ty)
+        c.emplace_back(plan_cost(bank.m, items, n, nw, ty), ty);
     std::stable_sort(c.begin(), c.end(),
                      [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
                          return a.first < b.first;
@@ -845,15 +1027,18 @@ std::vector<int> tile_candidates(int m, const AdvanceItem *items, int n, int nw,
 
 // Tile shape: columns are fixed by the q-row width (TX = 64 - 2r); the row
 // count comes from the tuning table if measured, else from the cost model
-// (fewest rounds of 256 workgroups times pipeline steps per tile).
-void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw, int forced_ty)
+// (fewest rounds of 256 workgroups times pipeline steps per tile), within
+// what the variant's LDS allows.
+void make_plan(const FusedBank &bank, int prec, const AdvanceItem *items, int n, Plan *plan,
+               int nw, int forced_ty)
 {
-    const int R = (m - 1) / 2, TX = kQW - 2 * R;
+    const int m = bank.m, R = (m - 1) / 2, TX = kQW - 2 * R;
+    const int hi = std::max(kMinTileRows, max_tile_rows(bank, prec, nw));
     int best_ty = forced_ty;
     if (best_ty <= 0) {
         double best = 1e300;
         best_ty = kMinTileRows;
-        for (int ty = kMinTileRows; ty <= kMaxTileRows; ++ty) {
+        for (int ty = kMinTileRows; ty <= hi; ++ty) {
             const double cost = plan_cost(m, items, n, nw, ty);
             if (cost < best - 1e-9) {
                 best = cost;
@@ -861,9 +1046,10 @@ void make_plan(int m, const AdvanceItem *items, int n, Plan *plan, int nw, int f
             }
         }
     }
-    best_ty = std::min(std::max(best_ty, kMinTileRows), kMaxTileRows);
+    best_ty = std::min(std::max(best_ty, kMinTileRows), hi);
     plan->tile_w = TX;
     plan->tile_h = best_ty;
+    plan->waves = nw;
     plan->njobs = n;
     plan->ntiles = 0;
     plan->jobs_ntx.assign(n, 0);
@@ -880,7 +1066,7 @@ size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(J
 size_t fused_table_bytes(int n) { return (size_t)std::max(n, 1) * sizeof(JobDesc); }
 
 hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
-                     hipStream_t s, const TuneTable *tune, int only_prec, int forced_ty)
+                     hipStream_t s, const TuneTable *tune, int only_prec, TileChoice forced)
 {
     // Jobs run in groups of equal precision (one kernel per precision); each
     // group has its own slice of the job table and its own plan.
@@ -894,20 +1080,22 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         if (grp.empty()) continue;
         const int gn = (int)grp.size();
         Plan plan;
-        int ty = forced_ty;
-        if (ty <= 0 && tune) ty = tune->lookup(batch_key(prec, grp.data(), gn));
-        make_plan(bank.m, grp.data(), gn, &plan, waves_for(prec), ty);
+        TileChoice ch = forced;
+        if (ch.waves <= 0 && ch.ty <= 0 && tune) ch = tune->lookup(batch_key(prec, grp.data(), gn));
+        if (ch.waves <= 0 || max_tile_rows(bank, prec, ch.waves) <= 0)
+            ch.waves = bank_default_waves(bank, prec);
+        make_plan(bank, prec, grp.data(), gn, &plan, ch.waves, ch.ty);
         JobDesc *dj = table + slot;
         slot += gn;
         int max_it = 0, base = 0;
         for (int c0 = 0; c0 < gn; c0 += kChunk) {
-            JobChunk ch{};
-            ch.first = c0;
-            ch.count = std::min(kChunk, gn - c0);
-            for (int i = 0; i < ch.count; ++i) {
+            JobChunk jc{};
+            jc.first = c0;
+            jc.count = std::min(kChunk, gn - c0);
+            for (int i = 0; i < jc.count; ++i) {
                 const AdvanceItem &it = grp[c0 + i];
                 const fe_job &j = *it.job;
-                JobDesc &d = ch.d[i];
+                JobDesc &d = jc.d[i];
                 const size_t plane = (size_t)j.height * j.width;
                 d.counts = j.counts;
                 d.ua = it.state;
@@ -928,12 +1116,12 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
                                   : j.data_term;
                 max_it = std::max(max_it, d.iters);
             }
-            write_jobs_kernel<<<1, kChunk, 0, s>>>(ch, dj);
+            write_jobs_kernel<<<1, kChunk, 0, s>>>(jc, dj);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         for (int it = 0; it < max_it; ++it) {
-            hipError_t e = launch_any(prec, bank, dj, gn, plan.ntiles, it, plan.tile_h, s);
+            hipError_t e = launch_any(prec, plan.waves, bank, dj, gn, plan.ntiles, it, plan.tile_h, s);
             if (e != hipSuccess) return e;
         }
     }

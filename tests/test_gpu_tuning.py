@@ -93,15 +93,20 @@ def test_autotune_and_forced_heights_are_bitwise(fe, torch, tmp_path):
     path = tmp_path / "tune.txt"
     fe._check(fe.library().fe_tuning_save(prior.handle, str(path).encode()))
     lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
-    keys = sorted(ln.split()[1] for ln in lines)
+    keys = sorted(ln.split()[2] for ln in lines)
     # one entry per precision group of the batch, keyed by its image sizes
     assert keys == ["p0:96x130,150x150,", "p1:64x64,", "p2:200x70,"], keys
-    for ty in (8, 13, 64, 128):
-        forced = tmp_path / ("forced%d.txt" % ty)
-        forced.write_text("".join("%d %s\n" % (ty, key) for key in keys))
+    for ln in lines:
+        nw, ty, key = ln.split()
+        assert int(nw) in ((8, 12) if key.startswith("p0") else (12,)), ln
+    # every variant and height gives the same bits: 8 or 12 waves for FP32
+    for nw32, ty in ((8, 8), (12, 13), (8, 64), (12, 96), (8, 128)):
+        forced = tmp_path / ("forced%d_%d.txt" % (nw32, ty))
+        forced.write_text("".join("%d %d %s\n" % (nw32 if key.startswith("p0") else 12,
+                                                  min(ty, 128), key) for key in keys))
         p2 = fe.Prior(k, a)
         fe._check(fe.library().fe_tuning_load(p2.handle, str(forced).encode()))
-        print("forced tile height %d" % ty, flush=True)
+        print("forced FP32 waves %d, tile height %d" % (nw32, ty), flush=True)
         _equal(torch, ref, fe.denoise_jobs(p2, specs))
     torch.cuda.synchronize()
 
@@ -111,7 +116,9 @@ def test_tuning_file_errors(fe, torch, tmp_path):
     prior = fe.Prior(k, a)
     lib = fe.library()
     assert lib.fe_tuning_load(prior.handle, str(tmp_path / "missing").encode()) == fe.FE_ERR_INVALID
-    for bad in ("7 p0:64x64,\n", "129 p0:64x64,\n", "x p0:64x64,\n"):
+    for bad in ("8 7 p0:64x64,\n", "8 129 p0:64x64,\n", "12 97 p0:64x64,\n",
+                "8 64 p1:64x64,\n", "10 64 p0:64x64,\n", "x 64 p0:64x64,\n",
+                "64 p0:64x64,\n"):
         f = tmp_path / "bad.txt"
         f.write_text(bad)
         assert lib.fe_tuning_load(prior.handle, str(f).encode()) == fe.FE_ERR_INVALID
