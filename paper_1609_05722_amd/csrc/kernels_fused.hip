@@ -191,6 +191,7 @@ struct MathF32 {
     static constexpr int NA = NFB * 4 * G::NTB;          // adjoint operands per lane
     static constexpr int SA = odd_quads(NA), SL = odd_quads(NFB * 4);
     static constexpr int kTabFloats = LDS ? 64 * (SA + 2 * SL) : 0;
+    static constexpr bool kPairTile = false;
     static constexpr int RB = LDS ? 1 : NFB;             // register-resident copies
     float afwd[G::KF][NFB];
     float badj[RB][LDS ? 1 : 4][LDS ? 1 : G::NTB];
@@ -367,6 +368,10 @@ struct MathP16 {
     // a lane's 8 values are consecutive in the LDS tile.  Otherwise taps are
     // packed densely, 32 per k-step.
     static constexpr bool PAD = (M == 7);
+    // M = 7: the LDS u tile holds, at every column c, the packed pair
+    // (u[c], u[c + 1]) in P, converted once per launch; a lane's 8 values
+    // of a k-step are then 4 aligned 32-bit words.
+    static constexpr bool kPairTile = PAD;
     static constexpr int KS = PAD ? 2 : (G::T + 31) / 32;    // forward k-steps
     static constexpr int KA = (NFB + 1) / 2;       // adjoint k-steps (32 filters)
     static constexpr int NTBP = (G::T + 15) / 16;  // adjoint tap blocks
@@ -378,6 +383,15 @@ struct MathP16 {
     };
 
     static __device__ void stage(float *, const void *, const void *, const void *, int, int) {}
+
+    // The pair tile's word: lo = P(a), hi = P(b), each rounded to nearest even.
+    static __device__ __forceinline__ float pack_pair(float a, float b)
+    {
+        const P pa = (P)a, pb = (P)b;
+        const unsigned w = (unsigned)__builtin_bit_cast(unsigned short, pa) |
+                           ((unsigned)__builtin_bit_cast(unsigned short, pb) << 16);
+        return __builtin_bit_cast(float, w);
+    }
 
     __device__ void load(const void *t0, const void *t1, const void *, const void *, int lane,
                          const float *)
@@ -415,9 +429,9 @@ struct MathP16 {
         for (int s = 0; s < KS; ++s) {
             vec8 b;
             if constexpr (PAD) {
-                const float *q = Ub + boff[s][0];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) b[e] = (P)q[e];
+                const unsigned *q = (const unsigned *)Ub + boff[s][0];
+                const u32x4 w = {q[0], q[2], q[4], q[6]};
+                b = __builtin_bit_cast(vec8, w);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) b[e] = (P)Ub[boff[s][e]];
@@ -543,9 +557,19 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int ur = i / G::US, uc = i - ur * G::US;
         const int yy = sym_clamp(y0 - 2 * R + ur, H);
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
-        U[ur * G::US + uc] = ucur[(long)yy * W + xx];
+        if constexpr (Math::kPairTile) {
+            const int xx1 = sym_clamp(x0 - 2 * R + uc + 1, W);
+            U[ur * G::US + uc] = Math::pack_pair(ucur[(long)yy * W + xx], ucur[(long)yy * W + xx1]);
+        } else {
+            U[ur * G::US + uc] = ucur[(long)yy * W + xx];
+        }
     }
     Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
+    // Every global load of the prologue (operand tables, u tile) has landed:
+    // said explicitly, so that the compiler's wait counting does not carry
+    // them into the step loop, where a conservative wait would also wait
+    // for the prefetches issued there.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     const int nq = ty + 2 * R;                 // q-rows of the tile
@@ -598,13 +622,14 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     };
     // ---- output rows: g = sum over ghosts and a of H; iPiano update --------
     // Inputs of the row a wave will finish are fetched one step ahead.
-    float pf_up = 0.0f, pf_y = 0.0f;
+    float pf_up = 0.0f, pf_y = 0.0f, pf_u = 0.0f;
     auto prefetch = [&](int st) {
         const int orow = st * NW - 2 * R + wave;
         if (orow >= 0 && orow < ty && lane < tx) {
             const long pix = (long)(y0 + orow) * W + x0 + lane;
             pf_up = uprev[pix];
             pf_y = counts[pix];
+            if constexpr (Math::kPairTile) pf_u = ucur[pix];   // the tile holds P pairs
         }
     };
     auto finalize = [&](int st) {
@@ -650,7 +675,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         gsum += row_sum(y);
         if (y >= H - R) gsum += row_sum(2 * H - 1 - y);
         if (lane >= tx) return;
-        const float uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
+        float uc;
+        if constexpr (Math::kPairTile) uc = pf_u;
+        else uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
         const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
         uprev[(long)y * W + x] = prox(ut, anscombe(pf_y), J.tl, J.data_term);
     };
