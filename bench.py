@@ -315,7 +315,7 @@ def main():
                                        log=lambda t: print(t, file=sys.stderr, flush=True))
     if not args.no_serving:
         from paper_1609_05722_amd.serving import serving_report
-        result["serving"] = serving_report(prior, args.serving_requests, (0.9,), "bf16")
+        result["serving"] = serving_report(prior, args.serving_requests, (0.5, 0.9), "bf16")
     if not args.no_cpu:
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
         result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)

@@ -67,6 +67,10 @@ def library():
             raise ImportError("libfe.so is not built: run "
                               "python -m paper_1609_05722_amd.build or "
                               "__graft_entry__.build()")
+        # PyTorch bundles its own HIP runtime under the same soname; loading
+        # it first makes libfe.so bind to that one copy (a second runtime
+        # loaded ahead of it leaves PyTorch without devices).
+        _torch()
         lib = ctypes.CDLL(LIB_PATH)
         i32, vp, sz = ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
         lib.fe_create.argtypes = [ctypes.POINTER(_Prior), ctypes.c_int, ctypes.POINTER(vp)]
@@ -157,12 +161,16 @@ class Prior:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
-            self._lib.fe_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fe_destroy(h)
+            self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: modules already torn down
+            pass
 
 
 @dataclass

@@ -101,12 +101,16 @@ class Server:
         return p.value, a.value, t.value
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
-            self._lib.fe_server_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fe_server_destroy(h)
+            self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: modules already torn down
+            pass
 
 
 def run_stream(server, arrivals, specs, timeout_s=600.0):
