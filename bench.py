@@ -72,11 +72,29 @@ def cpu_baseline(args, k, a, job, tau, gamma):
     oracle.denoise(y, k, a, job.lam, tau, gamma, its, job.data_term)
     dt = time.perf_counter() - t0
     px_it = job.height * job.width * its
+    # the same oracle on one host thread, on a 256 x 256 crop for 20 iterations
+    oracle.set_threads(1)
+    crop = np.ascontiguousarray(y[:256, :256])
+    t1 = time.perf_counter()
+    oracle.denoise(crop, k, a, job.lam, tau, gamma, 20, job.data_term)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": px_it / dt / 1e6, "unit": "Mpixel-iter/s", "cores": threads,
             "kind": "oracle", "seconds": dt,
             "sample": "one %dx%d image (peak %g), %d iterations, %d %dx%d filters, FP64"
                       % (job.height, job.width, job.peak, its, k.shape[0], k.shape[1],
-                         k.shape[2])}
+                         k.shape[2]),
+            "cpu_model": model,
+            "single_core": {"value": crop.size * 20 / dt1 / 1e6, "unit": "Mpixel-iter/s",
+                            "cores": 1, "seconds": dt1,
+                            "sample": "256x256 crop of the same image, 20 iterations"}}
 
 
 def batch_report(fe, torch, prior, args, tau, gamma, log=None):
