@@ -29,14 +29,18 @@
  *     error nothing is enqueued and fe_last_error() (thread-local) holds a
  *     message;
  *   - image buffers are row-major float32 on the device, owned by the
- *     caller; the library never frees caller memory and never allocates
- *     per call: scratch comes from the caller's workspace;
+ *     caller; the library never frees caller memory, and the denoising
+ *     calls (fe_denoise, fe_begin / fe_advance / fe_end, fe_denoise_binned,
+ *     fe_energy_grad) never allocate: scratch comes from the caller's
+ *     workspace.  fe_create, fe_autotune, fe_advance_graph_create and
+ *     fe_server_create allocate what they document;
  *   - work is enqueued asynchronously on the caller's HIP stream
  *     (hipStream_t passed as void*, NULL = the null stream); a device fault
  *     is reported as FE_ERR_DEVICE by a later call or by the caller's own
  *     synchronisation;
- *   - an fe_ctx is immutable after fe_create and may be used from several
- *     threads and streams at once, each with its own workspace.
+ *   - an fe_ctx may be used from several threads and streams at once, each
+ *     with its own workspace; its filter bank is immutable after fe_create,
+ *     its tuning table (fe_autotune, fe_tuning_load) is internally locked.
  */
 #ifndef FE_H
 #define FE_H
@@ -66,7 +70,8 @@ typedef int32_t fe_status;
  * influence, the inertial step, the prox and I_C are FP32 in every mode. */
 #define FE_PREC_FP32 0
 #define FE_PREC_BF16 1 /* bf16 operands, fp32 accumulation */
-#define FE_PREC_FP16 2 /* fp16 operands, fp32 accumulation */
+#define FE_PREC_FP16 2 /* fp16 operands, fp32 accumulation; u = f_A(y) must
+                          stay below the fp16 maximum 65504, y < ~1.07e9 */
 
 /* The learned prior of eq. 2.5: N_f filters of m x m taps with weights. */
 typedef struct {

@@ -238,27 +238,36 @@ def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25,
 
 
 def serving_report(prior, n_requests, loads=(0.9,), precision="bf16", max_side=2048,
-                   log=None):
+                   log=None, forms=("batched", "single")):
     """Both serving forms on the same request stream: saturation (every
     request at t = 0) and each offered load as a fraction of the form's own
-    saturation rate; mean PSNR at saturation for the equal-quality check."""
+    saturation rate; mean PSNR at saturation for the equal-quality check.
+    `log` receives one JSON line per finished run."""
     res = {"requests": n_requests, "contraction_precision": precision}
-    for mode, batched, prec in (("batched_" + precision, True, precision),
-                                ("single_fp32", False, "fp32")):
+    runs = {"batched": ("batched_" + precision, True, precision),
+            "single": ("single_fp32", False, "fp32")}
+    for form in forms:
+        mode, batched, prec = runs[form]
         _, specs, pxit, crops = build_requests(n_requests, 1e9, prec, hi=max_side)
         sat = serve(prior, np.zeros(len(specs)), specs, pxit, batched, crops=crops)
+        del specs
         out = {"saturation": sat}
+        if log:
+            log(json.dumps({mode: {"saturation": sat}}))
         for load in loads:
             times, specs, pxit, _ = build_requests(n_requests, load * sat["images_per_s"], prec,
                                                    hi=max_side)
             out["load_%g" % load] = serve(prior, times, specs, pxit, batched)
+            del specs
+            if log:
+                log(json.dumps({mode: {"load_%g" % load: out["load_%g" % load]}}))
         res[mode] = out
-        if log:
-            log(json.dumps({mode: out}))
-    b, f = res["batched_" + precision], res["single_fp32"]
-    res["dpsnr_db"] = round(b["saturation"]["mean_psnr_db"] - f["saturation"]["mean_psnr_db"], 4)
-    res["speedup_images_per_s"] = round(b["saturation"]["images_per_s"]
-                                        / f["saturation"]["images_per_s"], 3)
+    if "batched_" + precision in res and "single_fp32" in res:
+        b, f = res["batched_" + precision], res["single_fp32"]
+        res["dpsnr_db"] = round(b["saturation"]["mean_psnr_db"]
+                                - f["saturation"]["mean_psnr_db"], 4)
+        res["speedup_images_per_s"] = round(b["saturation"]["images_per_s"]
+                                            / f["saturation"]["images_per_s"], 3)
     return res
 
 
@@ -270,11 +279,14 @@ def main(argv=None):
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9,1.0,1.25")
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--max-side", type=int, default=2048)
+    ap.add_argument("--forms", default="batched,single",
+                    help="batched (continuous batching), single (one FP32 image at a time)")
     a = ap.parse_args(argv)
     k, al = prior_for(7, 48)
     prior = Prior(k, al)
     res = serving_report(prior, a.requests, [float(x) for x in a.loads.split(",")],
-                         a.precision, a.max_side, log=lambda s: print(s, flush=True))
+                         a.precision, a.max_side, log=lambda s: print(s, flush=True),
+                         forms=tuple(a.forms.split(",")))
     print(json.dumps(res))
 
 
