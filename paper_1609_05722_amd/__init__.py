@@ -346,6 +346,7 @@ class Batch:
     def capture(self, counts):
         """A HIP graph of one advance by counts (even) from the current
         iteration counts; each replay() applies them again."""
+        self.release_graph()
         cnt = (ctypes.c_int32 * max(1, self.n))(*[int(c) for c in counts])
         h = ctypes.c_void_p()
         _check(library().fe_advance_graph_create(self.prior.handle, self.arr, self._sp,
@@ -363,6 +364,12 @@ class Batch:
         if getattr(self, "_graph", None) is not None:
             library().fe_graph_destroy(self._graph)
             self._graph = None
+
+    def __del__(self):
+        try:
+            self.release_graph()
+        except Exception:   # interpreter shutdown: modules already torn down
+            pass
 
     def autotune(self, trial_iterations=4):
         _check(library().fe_autotune(self.prior.handle, self.arr, self.n,

@@ -533,8 +533,9 @@ fe_status fe_tuning_load(const fe_ctx *c, const char *path)
     if (!c || !path) return fail(FE_ERR_INVALID, "ctx and path must be non-NULL");
     std::ifstream f(path);
     if (!f) return fail(FE_ERR_INVALID, "cannot read %s", path);
+    // parse the whole file first: a malformed file changes nothing
     std::string line;
-    int loaded = 0;
+    std::vector<std::pair<std::string, fe::TileChoice>> entries;
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#') continue;
         std::istringstream ls(line);
@@ -548,9 +549,9 @@ fe_status fe_tuning_load(const fe_ctx *c, const char *path)
         if (hi <= 0 || ty < fe::kMinTileRows || ty > hi)
             return fail(FE_ERR_INVALID, "tuning line out of range (waves %d, height %d): %s",
                         nw, ty, line.c_str());
-        c->tune.store(key, fe::TileChoice{nw, ty});
-        ++loaded;
+        entries.emplace_back(key, fe::TileChoice{nw, ty});
     }
+    for (auto &kv : entries) c->tune.store(kv.first, kv.second);
     return FE_OK;
 }
 

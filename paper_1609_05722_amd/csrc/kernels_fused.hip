@@ -43,6 +43,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -755,13 +756,18 @@ hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, 
     constexpr int NW = Math::kNW;
     if (ty_max > rows_limit<M, Math>()) return hipErrorInvalidValue;
     const size_t bytes = lds_bytes<M, Math>(ty_max);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes<M, Math>(rows_limit<M, Math>()));
+    // the dynamic-LDS limit is raised once per device (any thread)
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+    if (!bit || !(attr_set.load(std::memory_order_acquire) & bit)) {
+        e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_bytes<M, Math>(rows_limit<M, Math>()));
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.fetch_or(bit, std::memory_order_release);
     }
     fused_step_kernel<M, Math><<<ntiles, 64 * NW, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
                                                                tabs[2], tabs[3], iter, ty_max);

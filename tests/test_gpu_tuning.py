@@ -122,3 +122,21 @@ def test_tuning_file_errors(fe, torch, tmp_path):
         f = tmp_path / "bad.txt"
         f.write_text(bad)
         assert lib.fe_tuning_load(prior.handle, str(f).encode()) == fe.FE_ERR_INVALID
+
+
+def test_tuning_load_is_all_or_nothing(fe, torch, tmp_path):
+    """A file with a good line before a bad one changes nothing."""
+    k, a = prior_for(7, 48)
+    prior = fe.Prior(k, a)
+    lib = fe.library()
+    f = tmp_path / "mixed.txt"
+    f.write_text("12 64 p0:64x64,\n8 999 p0:64x64,\n")
+    assert lib.fe_tuning_load(prior.handle, str(f).encode()) == fe.FE_ERR_INVALID
+    out = tmp_path / "saved.txt"
+    fe._check(lib.fe_tuning_save(prior.handle, str(out).encode()))
+    assert [ln for ln in out.read_text().splitlines() if not ln.startswith("#")] == []
+    f.write_text("# comment\n12 64 p0:64x64,\n\n8 100 p0:64x64,128x128,\n")
+    fe._check(lib.fe_tuning_load(prior.handle, str(f).encode()))
+    fe._check(lib.fe_tuning_save(prior.handle, str(out).encode()))
+    assert sorted(ln for ln in out.read_text().splitlines() if not ln.startswith("#")) == \
+        ["12 64 p0:64x64,", "8 100 p0:64x64,128x128,"]
