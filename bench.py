@@ -78,6 +78,18 @@ def cpu_baseline(args, k, a, job, tau, gamma):
     t1 = time.perf_counter()
     oracle.denoise(crop, k, a, job.lam, tau, gamma, 20, job.data_term)
     dt1 = time.perf_counter() - t1
+    # the oracle-size case (64 x 64, peak 4, 24 filters of 5 x 5, 100 iterations)
+    from synth.workloads import oracle_config, prior_for, step_size_for
+    small = oracle_config()["jobs"][0]
+    ks, as_ = prior_for(5, 24)
+    ts, gs = step_size_for(5, 24)
+    _, ys = small.arrays()
+    small_rates = {}
+    for n_thr in (1, threads):
+        oracle.set_threads(n_thr)
+        t2 = time.perf_counter()
+        oracle.denoise(ys, ks, as_, small.lam, ts, gs, small.iterations, small.data_term)
+        small_rates["cores_%d" % n_thr] = ys.size * small.iterations / (time.perf_counter() - t2) / 1e6
     oracle.set_threads(threads)
     model = None
     try:
@@ -94,7 +106,9 @@ def cpu_baseline(args, k, a, job, tau, gamma):
             "cpu_model": model,
             "single_core": {"value": crop.size * 20 / dt1 / 1e6, "unit": "Mpixel-iter/s",
                             "cores": 1, "seconds": dt1,
-                            "sample": "256x256 crop of the same image, 20 iterations"}}
+                            "sample": "256x256 crop of the same image, 20 iterations"},
+            "oracle_size_case": dict(small_rates, unit="Mpixel-iter/s",
+                                     sample="64x64, peak 4, 24 5x5 filters, 100 iterations")}
 
 
 def batch_report(fe, torch, prior, args, tau, gamma, log=None):

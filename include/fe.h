@@ -38,6 +38,11 @@
  *     (hipStream_t passed as void*, NULL = the null stream); a device fault
  *     is reported as FE_ERR_DEVICE by a later call or by the caller's own
  *     synchronisation;
+ *   - debug mode: with the environment variable FE_VALIDATE=1, fe_denoise,
+ *     fe_begin, fe_denoise_binned and fe_energy_grad first run a device pass
+ *     over the counts and return FE_ERR_INVALID if any is negative, NaN or
+ *     infinite (the pass allocates a few flags and synchronises the stream;
+ *     it is skipped while the stream is being captured into a graph);
  *   - an fe_ctx may be used from several threads and streams at once, each
  *     with its own workspace; its filter bank is immutable after fe_create,
  *     its tuning table (fe_autotune, fe_tuning_load) is internally locked.
@@ -250,15 +255,19 @@ fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,
 /* Energy E(u) = E_FoE(u) + D(u, v) (eq. 2.5 with eq. 3.4 or 3.6) and its
  * gradient, at an Anscombe-domain image u (DEVICE H*W) for counts y
  * (DEVICE H*W, v = f_A(y)).  data_term is FE_DATA_QUADRATIC or
- * FE_DATA_IDIV.  If `energy` (HOST) is not NULL the call synchronises the
- * stream and stores E there; with the I-divergence term E is +inf when any
- * u <= 0.  If `grad` (DEVICE H*W) is not NULL it receives grad E.  Sums are
- * accumulated in FP32 per workgroup and combined in FP64 in a fixed order,
- * so the result is deterministic. */
+ * FE_DATA_IDIV.  precision (FE_PREC_*) rounds the operands of both
+ * filter-bank contractions (u and k_i for K_i u; psi_i and k_i for
+ * K_i^T psi_i) to that format, products accumulated in FP32; the influence,
+ * log(1 + z^2) and the data term stay FP32.  If `energy` (HOST) is not NULL
+ * the call synchronises the stream and stores E there; with the I-divergence
+ * term E is +inf when any u <= 0.  If `grad` (DEVICE H*W) is not NULL it
+ * receives grad E.  Sums are accumulated in FP32 per workgroup and combined
+ * in FP64 in a fixed order, so the result is deterministic. */
 fe_status fe_energy_grad(const fe_ctx *ctx, int32_t height, int32_t width,
                          const float *counts, const float *u, float lambda,
-                         int32_t data_term, double *energy, float *grad,
-                         void *workspace, size_t ws_bytes, void *hip_stream);
+                         int32_t data_term, int32_t precision, double *energy,
+                         float *grad, void *workspace, size_t ws_bytes,
+                         void *hip_stream);
 
 /* Release the context (NULL is allowed). */
 void fe_destroy(fe_ctx *ctx);

@@ -83,7 +83,7 @@ def library():
         lib.fe_denoise.restype = i32
         lib.fe_energy_grad_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
         lib.fe_energy_grad_workspace_size.restype = i32
-        lib.fe_energy_grad.argtypes = [vp, i32, i32, vp, vp, ctypes.c_float, i32,
+        lib.fe_energy_grad.argtypes = [vp, i32, i32, vp, vp, ctypes.c_float, i32, i32,
                                        ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
         lib.fe_energy_grad.restype = i32
         pp = ctypes.POINTER(ctypes.c_void_p)
@@ -288,7 +288,7 @@ def denoise(counts, prior, lam, iterations, tau, gamma, data_term="auto",
 
 
 def energy_grad(counts, u, prior, lam, data_term, want_energy=True,
-                want_grad=True, stream=None):
+                want_grad=True, stream=None, precision="fp32"):
     """E(u) and grad E(u) for counts y (v = f_A(y)) and an Anscombe-domain
     image u.  Returns (energy float or None, grad tensor or None)."""
     torch = _torch()
@@ -301,8 +301,9 @@ def energy_grad(counts, u, prior, lam, data_term, want_energy=True,
     ws = alloc_workspace(sz.value, c.device)
     grad = torch.empty_like(uu) if want_grad else None
     e = ctypes.c_double()
+    pr = _PREC[precision] if isinstance(precision, str) else int(precision)
     _check(library().fe_energy_grad(prior.handle, H, W, _ptr(c), _ptr(uu), float(lam),
-                                    dt, ctypes.byref(e) if want_energy else None,
+                                    dt, pr, ctypes.byref(e) if want_energy else None,
                                     _ptr(grad), _ptr(ws), ws.numel(),
                                     _stream_handle(stream)))
     return (e.value if want_energy else None), grad

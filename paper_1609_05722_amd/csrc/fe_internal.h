@@ -39,6 +39,10 @@ hipError_t launch_anscombe_init(const float *counts, float *u0, float *u1,
 hipError_t launch_inverse_anscombe(const float *u, float *out,
                                    float *out_anscombe, long n, hipStream_t s);
 hipError_t launch_bin3(const float *y, int H, int W, float *yb, hipStream_t s);
+// Debug validation: bad[0] |= 1 if any of y[0..n) is negative, NaN or
+// infinite; launch_zero_ints clears n flags first.
+hipError_t launch_check_counts(const float *y, long n, int *bad, hipStream_t s);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_upsample3(const float *xb, int Hb, int Wb, float *x, int H, int W,
                             hipStream_t s);
 
@@ -46,11 +50,13 @@ hipError_t launch_upsample3(const float *xb, int Hb, int Wb, float *x, int H, in
 // psi_i = alpha_i rho'(K_i u) for all filters, written as nf planes of H*W.
 // If rho_partial != NULL every block also writes its FP32 partial sum of
 // alpha_i rho(K_i u) (and data_partial the data-term sum when counts != NULL).
+// precision (FE_PREC_*) rounds the operands of K_i u (FP32 accumulation).
 hipError_t launch_direct_forward(const DeviceBank &bank, const float *u,
                                  int H, int W, float *psi,
                                  float *rho_partial, float *data_partial,
                                  const float *counts, float lambda,
-                                 int data_term, int *n_blocks, hipStream_t s);
+                                 int data_term, int precision, int *n_blocks,
+                                 hipStream_t s);
 // u_next = prox(u - tau * sum_i K_i^T psi_i + gamma (u - u_prev)); u_next may
 // alias u_prev (each pixel is read before it is written by one thread).
 hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
@@ -58,11 +64,12 @@ hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
                                       const float *counts, float *u_next,
                                       int H, int W, StepParams p,
                                       hipStream_t s);
-// grad = sum_i K_i^T psi_i + grad D(u, v).
+// grad = sum_i K_i^T psi_i + grad D(u, v); precision rounds the operands
+// of K_i^T psi_i (FP32 accumulation).
 hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,
                                       const float *u, const float *counts,
                                       float *grad, int H, int W, float lambda,
-                                      int data_term, hipStream_t s);
+                                      int data_term, int precision, hipStream_t s);
 int direct_forward_blocks(int H, int W);
 
 }  // namespace fe

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <fstream>
 #include <sstream>
 #include <cstdarg>
@@ -173,6 +174,51 @@ fe_status enqueue_end(const fe_job *jobs, float *const *states, const int32_t *d
     return FE_OK;
 }
 
+// Debug mode (environment FE_VALIDATE=1): before the counts are used, a
+// device pass rejects negative, NaN or infinite values.  It allocates a few
+// flags, synchronises the stream and is skipped while the stream is being
+// captured into a graph.
+bool validation_enabled()
+{
+    const char *v = std::getenv("FE_VALIDATE");
+    return v && v[0] == '1' && v[1] == 0;
+}
+
+fe_status validate_counts(const float *const *planes, const long *sizes, int n, hipStream_t s)
+{
+    if (!validation_enabled() || n <= 0) return FE_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return FE_OK;
+    int *flags = nullptr;
+    hipError_t e = hipMalloc((void **)&flags, sizeof(int) * n);
+    if (e != hipSuccess) return hip_fail(e, "validation flags");
+    std::vector<int> h(n, 0);
+    e = fe::launch_zero_ints(flags, n, s);
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = fe::launch_check_counts(planes[i], sizes[i], flags + i, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), flags, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(flags);
+    if (e != hipSuccess) return hip_fail(e, "validation");
+    for (int i = 0; i < n; ++i)
+        if (h[i]) return fail(FE_ERR_INVALID, "job %d: counts hold a negative, NaN or infinite value", i);
+    return FE_OK;
+}
+
+fe_status validate_jobs(const fe_job *jobs, int n, hipStream_t s)
+{
+    if (!validation_enabled()) return FE_OK;
+    std::vector<const float *> planes(n);
+    std::vector<long> sizes(n);
+    for (int i = 0; i < n; ++i) {
+        planes[i] = jobs[i].counts;
+        sizes[i] = (long)jobs[i].height * jobs[i].width;
+    }
+    return validate_counts(planes.data(), sizes.data(), n, s);
+}
+
 fe_status enqueue_advance(const fe_ctx *c, const fe_job *jobs, float *const *states,
                           const int32_t *done, const int32_t *count, int32_t n, void *table,
                           hipStream_t s)
@@ -282,6 +328,8 @@ fe_status fe_denoise(const fe_ctx *c, const fe_job *jobs, int32_t n,
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
+    st = validate_jobs(jobs, n, s);
+    if (st != FE_OK) return st;
     char *ws = (char *)workspace;
     std::vector<float *> states(n);
     std::vector<int32_t> zero(n, 0), iters(n);
@@ -317,6 +365,8 @@ fe_status fe_begin(const fe_ctx *c, const fe_job *jobs, float *const *states, in
     if (st != FE_OK || n == 0) return st;
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    st = validate_jobs(jobs, n, (hipStream_t)hip_stream);
+    if (st != FE_OK) return st;
     return enqueue_begin(jobs, states, n, (hipStream_t)hip_stream);
 }
 
@@ -427,6 +477,8 @@ fe_status fe_denoise_binned(const fe_ctx *c, const fe_job *jobs, int32_t n, void
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
+    st = validate_jobs(jobs, n, s);
+    if (st != FE_OK) return st;
     char *ws = (char *)workspace;
     for (int i = 0; i < n; ++i) {
         float *yb = (float *)(ws + L.yb_off[i]);
@@ -632,8 +684,9 @@ fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, s
 }
 
 fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *counts,
-                         const float *u, float lambda, int32_t data_term, double *energy,
-                         float *grad, void *workspace, size_t ws_bytes, void *hip_stream)
+                         const float *u, float lambda, int32_t data_term, int32_t precision,
+                         double *energy, float *grad, void *workspace, size_t ws_bytes,
+                         void *hip_stream)
 {
     size_t need = 0;
     fe_status st = fe_energy_grad_workspace_size(c, H, W, &need);
@@ -643,6 +696,8 @@ fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *cou
         return fail(FE_ERR_INVALID, "lambda must be finite and > 0");
     if (data_term != FE_DATA_QUADRATIC && data_term != FE_DATA_IDIV)
         return fail(FE_ERR_INVALID, "data term must be FE_DATA_QUADRATIC or FE_DATA_IDIV");
+    if (precision < FE_PREC_FP32 || precision > FE_PREC_FP16)
+        return fail(FE_ERR_INVALID, "precision %d is not an FE_PREC_* value", precision);
     if (!workspace || ((uintptr_t)workspace & 255))
         return fail(FE_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
     if (ws_bytes < need) return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
@@ -651,6 +706,11 @@ fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *cou
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
+    {
+        const long np = (long)H * W;
+        st = validate_counts(&counts, &np, 1, s);
+        if (st != FE_OK) return st;
+    }
     char *ws = (char *)workspace;
     const size_t plane = (size_t)H * W * sizeof(float);
     float *psi = (float *)ws;
@@ -660,11 +720,11 @@ fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *cou
     int nblocks = 0;
     hipError_t e = fe::launch_direct_forward(c->bank, u, H, W, psi, energy ? rho_part : nullptr,
                                              energy ? data_part : nullptr, counts, lambda,
-                                             data_term, &nblocks, s);
+                                             data_term, precision, &nblocks, s);
     if (e != hipSuccess) return hip_fail(e, "energy forward");
     if (grad) {
         e = fe::launch_direct_adjoint_grad(c->bank, psi, u, counts, grad, H, W, lambda,
-                                           data_term, s);
+                                           data_term, precision, s);
         if (e != hipSuccess) return hip_fail(e, "energy adjoint");
     }
     if (energy) {

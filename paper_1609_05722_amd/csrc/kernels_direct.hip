@@ -1,4 +1,4 @@
-// Direct FP32 filter-bank kernels: one thread per pixel, no matrix cores.
+// Direct filter-bank kernels: one thread per pixel, no matrix cores.
 //
 // These compute the prior's gradient of eq. 3.2 in two passes through HBM:
 // the forward pass writes psi_i = alpha_i rho'(K_i u) for every filter, the
@@ -13,6 +13,17 @@ namespace fe {
 namespace {
 
 constexpr int kBX = 16, kBY = 16;
+
+// Operand rounding of the contractions: FE_PREC_FP32 keeps the value,
+// FE_PREC_BF16 / FE_PREC_FP16 round it to nearest even in that format (the
+// products are then accumulated in FP32).
+template <int PREC>
+__device__ __forceinline__ float operand(float x)
+{
+    if constexpr (PREC == 1) return (float)(__bf16)x;
+    else if constexpr (PREC == 2) return (float)(_Float16)x;
+    else return x;
+}
 
 // Half-sample symmetric index (u(-1-i) = u(i), u(n+i) = u(n-1-i)), one
 // reflection, then clamped so that even an unused far ghost stays in bounds.
@@ -37,7 +48,7 @@ __device__ float block_sum(float v, float *red)
     return r;
 }
 
-template <int M>
+template <int M, int PREC>
 __global__ __launch_bounds__(kBX * kBY)
 void forward_kernel(const float *__restrict__ taps,
                     const float *__restrict__ alpha2,
@@ -59,7 +70,8 @@ void forward_kernel(const float *__restrict__ taps,
         for (int a = 0; a < M; ++a) {
             const int yy = sym(y + a - R, H);
 #pragma unroll
-            for (int b = 0; b < M; ++b) e[a * M + b] = u[(long)yy * W + sym(x + b - R, W)];
+            for (int b = 0; b < M; ++b)
+                e[a * M + b] = operand<PREC>(u[(long)yy * W + sym(x + b - R, W)]);
         }
     }
     float rho_acc = 0.0f;
@@ -69,7 +81,7 @@ void forward_kernel(const float *__restrict__ taps,
         const float *k = taps + i * M * M;
         float z = 0.0f;
 #pragma unroll
-        for (int t = 0; t < M * M; ++t) z = fmaf(k[t], e[t], z);
+        for (int t = 0; t < M * M; ++t) z = fmaf(operand<PREC>(k[t]), e[t], z);
         psi[i * plane + (long)y * W + x] = influence(z, alpha2[i]);
         if (rho_partial) rho_acc += alpha[i] * log1pf(z * z);
     }
@@ -95,7 +107,7 @@ void forward_kernel(const float *__restrict__ taps,
 // (psi = 0 outside the image), and every extended position mirroring
 // (y, x) adds onto it: the pixel itself, plus the ghost row -1-y (y < R) or
 // 2H-1-y (y >= H-R), likewise for columns.
-template <int M>
+template <int M, int PREC>
 __device__ float adjoint_at(const float *__restrict__ taps, int nf,
                             const float *__restrict__ psi, int H, int W,
                             int y, int x)
@@ -126,7 +138,8 @@ __device__ float adjoint_at(const float *__restrict__ taps, int nf,
                     for (int b = 0; b < M; ++b) {
                         const int qx = sx - b + R;
                         if (qx < 0 || qx >= W) continue;
-                        acc = fmaf(k[a * M + b], p[(long)qy * W + qx], acc);
+                        acc = fmaf(operand<PREC>(k[a * M + b]),
+                                   operand<PREC>(p[(long)qy * W + qx]), acc);
                     }
                 }
             }
@@ -148,13 +161,13 @@ void adjoint_step_kernel(const float *__restrict__ taps, int nf,
     const int y = blockIdx.y * kBY + threadIdx.y;
     if (x >= W || y >= H) return;
     const long p = (long)y * W + x;
-    const float g = adjoint_at<M>(taps, nf, psi, H, W, y, x);
+    const float g = adjoint_at<M, 0>(taps, nf, psi, H, W, y, x);
     const float uc = u[p];
     const float ut = inertial_step(uc, u_prev[p], g, prm.tau, prm.gamma);
     u_next[p] = prox(ut, anscombe(counts[p]), prm.tau_lambda, prm.data_term);
 }
 
-template <int M>
+template <int M, int PREC>
 __global__ __launch_bounds__(kBX * kBY)
 void adjoint_grad_kernel(const float *__restrict__ taps, int nf,
                          const float *__restrict__ psi,
@@ -167,7 +180,7 @@ void adjoint_grad_kernel(const float *__restrict__ taps, int nf,
     const int y = blockIdx.y * kBY + threadIdx.y;
     if (x >= W || y >= H) return;
     const long p = (long)y * W + x;
-    const float g = adjoint_at<M>(taps, nf, psi, H, W, y, x);
+    const float g = adjoint_at<M, PREC>(taps, nf, psi, H, W, y, x);
     grad[p] = g + lambda * data_gradient(u[p], anscombe(counts[p]), data_term);
 }
 
@@ -188,19 +201,33 @@ int direct_forward_blocks(int H, int W)
     case 7: CALL(7); break;    \
     default: return hipErrorInvalidValue; }
 
+#define FE_DISPATCH_MP(m, prec, CALL)                                        \
+    switch ((m) * 10 + (prec)) {                                             \
+    case 30: CALL(3, 0); break;                                              \
+    case 31: CALL(3, 1); break;                                              \
+    case 32: CALL(3, 2); break;                                              \
+    case 50: CALL(5, 0); break;                                              \
+    case 51: CALL(5, 1); break;                                              \
+    case 52: CALL(5, 2); break;                                              \
+    case 70: CALL(7, 0); break;                                              \
+    case 71: CALL(7, 1); break;                                              \
+    case 72: CALL(7, 2); break;                                              \
+    default: return hipErrorInvalidValue; }
+
 hipError_t launch_direct_forward(const DeviceBank &bank, const float *u,
                                  int H, int W, float *psi,
                                  float *rho_partial, float *data_partial,
                                  const float *counts, float lambda,
-                                 int data_term, int *n_blocks, hipStream_t s)
+                                 int data_term, int precision, int *n_blocks,
+                                 hipStream_t s)
 {
     const dim3 g = grid2d(H, W), b(kBX, kBY);
     if (n_blocks) *n_blocks = (int)(g.x * g.y);
-#define FE_CALL(MM)                                                          \
-    forward_kernel<MM><<<g, b, 0, s>>>(bank.taps, bank.alpha2, bank.alpha,    \
-                                       bank.nf, u, H, W, psi, rho_partial,    \
-                                       data_partial, counts, lambda, data_term)
-    FE_DISPATCH_M(bank.m, FE_CALL)
+#define FE_CALL(MM, PP)                                                      \
+    forward_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps, bank.alpha2, bank.alpha, \
+                                           bank.nf, u, H, W, psi, rho_partial, \
+                                           data_partial, counts, lambda, data_term)
+    FE_DISPATCH_MP(bank.m, precision, FE_CALL)
 #undef FE_CALL
     return hipGetLastError();
 }
@@ -223,14 +250,14 @@ hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
 hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,
                                       const float *u, const float *counts,
                                       float *grad, int H, int W, float lambda,
-                                      int data_term, hipStream_t s)
+                                      int data_term, int precision, hipStream_t s)
 {
     const dim3 g = grid2d(H, W), b(kBX, kBY);
-#define FE_CALL(MM)                                                          \
-    adjoint_grad_kernel<MM><<<g, b, 0, s>>>(bank.taps, bank.nf, psi, u,       \
-                                            counts, grad, H, W, lambda,       \
-                                            data_term)
-    FE_DISPATCH_M(bank.m, FE_CALL)
+#define FE_CALL(MM, PP)                                                      \
+    adjoint_grad_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps, bank.nf, psi, u,   \
+                                                counts, grad, H, W, lambda,   \
+                                                data_term)
+    FE_DISPATCH_MP(bank.m, precision, FE_CALL)
 #undef FE_CALL
     return hipGetLastError();
 }

@@ -90,6 +90,24 @@ __global__ void upsample3_kernel(const float *__restrict__ xb, int Hb, int Wb,
     }
 }
 
+// Flags (sets *bad = 1) if any count is negative, NaN or infinite.
+__global__ void check_counts_kernel(const float *__restrict__ y, long n, int *bad)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    bool any = false;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const float v = y[p];
+        any |= !(v >= 0.0f && v <= 3.0e38f);
+    }
+    if (any) atomicOr(bad, 1);
+}
+
+__global__ void zero_ints_kernel(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 int grid_for(long n)
 {
     long b = (n + 255) / 256;
@@ -99,6 +117,20 @@ int grid_for(long n)
 }
 
 }  // namespace
+
+hipError_t launch_check_counts(const float *y, long n, int *bad, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    check_counts_kernel<<<grid_for(n), 256, 0, s>>>(y, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    zero_ints_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_bin3(const float *y, int H, int W, float *yb, hipStream_t s)
 {

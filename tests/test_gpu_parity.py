@@ -289,3 +289,71 @@ def test_binned_variant(fe, torch, peak, shape):
     ub, xo = oracle.denoise_binned(y, k, a, lam, tau, gamma, 60, data_term_for_peak(9 * peak))
     assert _rel_err(ubg.cpu().numpy().astype(np.float64), ub) <= TOL
     assert _rel_err(xg.cpu().numpy().astype(np.float64), xo) <= TOL
+
+
+def _round_operand(x, precision):
+    """Round float32 values to bf16 / fp16 (nearest even), back to float32."""
+    x = np.ascontiguousarray(x, np.float32)
+    if precision == "fp16":
+        return x.astype(np.float16).astype(np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("data_term", [QUADRATIC, IDIV])
+def test_energy_and_gradient_reduced_precision(fe, torch, precision, data_term):
+    """Reduced-precision contractions in fe_energy_grad: the oracle's filter
+    banks applied to the rounded operands (u and k for K u; psi and k for
+    K^T psi), everything else as in FP32."""
+    prior, k, a = _prior(fe, 7, 48)
+    _, y = noisy_pair(23, 24, 53, 66, 2.0)
+    v = oracle.anscombe(y)
+    u32 = (v + np.random.default_rng(5).uniform(-0.3, 0.3, v.shape)).astype(np.float32)
+    lam = np.float32(30.0)
+    e, g = fe.energy_grad(torch.from_numpy(y).cuda(), torch.from_numpy(u32).cuda(),
+                          prior, float(lam), data_term, precision=precision)
+    ur = _round_operand(u32, precision).astype(np.float64)
+    kr = _round_operand(k, precision).astype(np.float64)
+    a64 = a.astype(np.float64)
+    z = oracle.filter_bank(ur, kr)
+    e_model = float(np.sum(a64[:, None, None] * np.log1p(z * z))) + \
+        oracle.energy_data(u32.astype(np.float64), v, lam, data_term)
+    psi = (2.0 * a64[:, None, None] * z / (1.0 + z * z)).astype(np.float32)
+    g_model = oracle.filter_adjoint(_round_operand(psi, precision).astype(np.float64), kr)
+    u64 = u32.astype(np.float64)
+    g_model += lam * ((u64 - v) if data_term == QUADRATIC else (1.0 - v / u64))
+    g = g.cpu().numpy().astype(np.float64)
+    d = np.max(np.abs(g - g_model)) / max(np.max(np.abs(g_model)), 1e-3)
+    print("energy_grad %s: energy rel %.2e, grad rel %.2e"
+          % (precision, abs(e - e_model) / abs(e_model), d), flush=True)
+    assert abs(e - e_model) <= 1e-4 * abs(e_model), (e, e_model)
+    # a psi value whose FP32 rounding differs by one ulp may round to the
+    # neighbouring bf16 / fp16 value: one operand ulp of slack
+    assert d <= (5e-3 if precision == "bf16" else 1e-3), d
+
+
+def test_validation_mode_rejects_bad_counts(fe, torch):
+    """FE_VALIDATE=1: negative, NaN or infinite counts are rejected before
+    any work; valid counts give the same bits as without validation."""
+    import os
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    _, y = noisy_pair(25, 26, 40, 50, 4.0)
+    good = torch.from_numpy(y).cuda()
+    ref = fe.denoise(good, prior, 30.0, 10, tau, gamma)
+    os.environ["FE_VALIDATE"] = "1"
+    try:
+        assert torch.equal(fe.denoise(good, prior, 30.0, 10, tau, gamma), ref)
+        for bad_value in (-1.0, float("nan"), float("inf")):
+            bad = good.clone()
+            bad[17, 23] = bad_value
+            with pytest.raises(fe.FeError) as err:
+                fe.denoise(bad, prior, 30.0, 10, tau, gamma)
+            assert err.value.status == fe.FE_ERR_INVALID
+            with pytest.raises(fe.FeError):
+                fe.energy_grad(bad, good, prior, 30.0, QUADRATIC)
+    finally:
+        del os.environ["FE_VALIDATE"]
+    torch.cuda.synchronize()
