@@ -113,17 +113,22 @@ class Server:
             pass
 
 
-def run_stream(server, arrivals, specs, timeout_s=600.0):
+def run_stream(server, arrivals, specs, timeout_s=600.0, progress_s=None):
     """Submit spec j at arrival time arrivals[j] (seconds from now) and
     collect every completion.  Returns (completions sorted by tag, outputs,
-    wall seconds)."""
+    wall seconds).  With progress_s, prints a progress line that often."""
     order = np.argsort(arrivals, kind="stable")
     done = {}
     outs = {}
     t0 = time.perf_counter()
+    next_report = progress_s
     i = 0
     n = len(specs)
     while len(done) < n:
+        if progress_s and time.perf_counter() - t0 >= next_report:
+            print("serving: %.0f s, %d of %d submitted, %d done"
+                  % (time.perf_counter() - t0, i, n, len(done)), flush=True)
+            next_report += progress_s
         now = time.perf_counter() - t0
         while i < n and arrivals[order[i]] <= now:
             j = int(order[i])
@@ -220,14 +225,16 @@ def mean_psnr(outs, crops, pool_side=2048, n_clean=4, seed=77):
     return float(np.mean(psnrs))
 
 
-def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25, crops=None):
+def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25, crops=None,
+          progress_s=None):
     """One serving run; batched: continuous batching, else one job at a time."""
     import torch
     srv = Server(prior, int(budget_gb * (1 << 30)),
                  iters_per_tick=iters_per_tick if batched else 1 << 20,
                  max_active=4096 if batched else 1, ticks_in_flight=2)
     try:
-        comps, outs, wall = run_stream(srv, times, specs)
+        comps, outs, wall = run_stream(srv, times, specs, timeout_s=1200.0,
+                                       progress_s=progress_s)
     finally:
         srv.close()
     torch.cuda.synchronize()
@@ -238,7 +245,7 @@ def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25,
 
 
 def serving_report(prior, n_requests, loads=(0.9,), precision="bf16", max_side=2048,
-                   log=None, forms=("batched", "single")):
+                   log=None, forms=("batched", "single"), progress_s=None):
     """Both serving forms on the same request stream: saturation (every
     request at t = 0) and each offered load as a fraction of the form's own
     saturation rate; mean PSNR at saturation for the equal-quality check.
@@ -249,7 +256,8 @@ def serving_report(prior, n_requests, loads=(0.9,), precision="bf16", max_side=2
     for form in forms:
         mode, batched, prec = runs[form]
         _, specs, pxit, crops = build_requests(n_requests, 1e9, prec, hi=max_side)
-        sat = serve(prior, np.zeros(len(specs)), specs, pxit, batched, crops=crops)
+        sat = serve(prior, np.zeros(len(specs)), specs, pxit, batched, crops=crops,
+                    progress_s=progress_s)
         del specs
         out = {"saturation": sat}
         if log:
@@ -257,7 +265,8 @@ def serving_report(prior, n_requests, loads=(0.9,), precision="bf16", max_side=2
         for load in loads:
             times, specs, pxit, _ = build_requests(n_requests, load * sat["images_per_s"], prec,
                                                    hi=max_side)
-            out["load_%g" % load] = serve(prior, times, specs, pxit, batched)
+            out["load_%g" % load] = serve(prior, times, specs, pxit, batched,
+                                          progress_s=progress_s)
             del specs
             if log:
                 log(json.dumps({mode: {"load_%g" % load: out["load_%g" % load]}}))
@@ -279,6 +288,8 @@ def main(argv=None):
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9,1.0,1.25")
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--max-side", type=int, default=2048)
+    ap.add_argument("--progress", type=float, default=30.0,
+                    help="seconds between progress lines during a run (0: none)")
     ap.add_argument("--forms", default="batched,single",
                     help="batched (continuous batching), single (one FP32 image at a time)")
     a = ap.parse_args(argv)
@@ -286,7 +297,7 @@ def main(argv=None):
     prior = Prior(k, al)
     res = serving_report(prior, a.requests, [float(x) for x in a.loads.split(",")],
                          a.precision, a.max_side, log=lambda s: print(s, flush=True),
-                         forms=tuple(a.forms.split(",")))
+                         forms=tuple(a.forms.split(",")), progress_s=a.progress)
     print(json.dumps(res))
 
 
