@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "fe.h"
+
 namespace fe {
 
 constexpr int kMaxM = 7;         // largest filter side built
@@ -45,6 +47,12 @@ hipError_t launch_check_counts(const float *y, long n, int *bad, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_upsample3(const float *xb, int Hb, int Wb, float *x, int H, int W,
                             hipStream_t s);
+
+// ---- debug validation of counts (fe_runtime.cpp) -------------------------
+// With FE_VALIDATE=1 in the environment: FE_ERR_INVALID (and the message in
+// fe_last_error) if any job's counts hold a negative, NaN or infinite
+// value; synchronous, on the null stream of `device`.  FE_OK otherwise.
+fe_status validate_job_counts(int device, const fe_job *jobs, int n);
 
 // ---- direct (non-MFMA) FP32 kernels (kernels_direct.hip) ------------------
 // psi_i = alpha_i rho'(K_i u) for all filters, written as nf planes of H*W.

@@ -232,6 +232,14 @@ fe_status enqueue_advance(const fe_ctx *c, const fe_job *jobs, float *const *sta
 
 }  // namespace
 
+fe_status fe::validate_job_counts(int device, const fe_job *jobs, int n)
+{
+    if (!validation_enabled() || n <= 0) return FE_OK;
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return validate_jobs(jobs, n, nullptr);
+}
+
 extern "C" {
 
 const char *fe_last_error(void) { return g_error.c_str(); }

@@ -22,6 +22,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "fe_internal.h"
 #include "fe_sched.h"
 
 namespace {
@@ -133,6 +134,7 @@ void fe_server::run()
     std::vector<float *> bs, as, es;
     std::vector<int32_t> done, cnt, edone;
     while (true) {
+        bool failed = false;
         {
             std::unique_lock<std::mutex> lk(mu);
             if (incoming.empty() && sched->pending() == 0 && sched->active() == 0 &&
@@ -146,8 +148,9 @@ void fe_server::run()
                 const uint64_t id = sched->submit(r.bytes, r.job.iterations, r.t_submit);
                 jobs.emplace(id, r);
             }
+            failed = status != FE_OK;
         }
-        if (status != FE_OK) break;
+        if (failed) break;
         while (retire_one(false)) {
         }
         if ((int)inflight.size() >= cfg.ticks_in_flight) {
@@ -294,6 +297,10 @@ fe_status fe_server_submit(fe_server *s, const fe_job *job, uint64_t tag)
     fe_state_bytes(s->ctx, job->height, job->width, &bytes);
     if (!s->sched->fits_ever(bytes))
         return srv_fail(FE_ERR_INVALID, "job state exceeds the server's memory budget");
+    // debug mode: reject bad counts here, on the caller's thread, rather than
+    // failing the whole server when the worker starts the job
+    st = fe::validate_job_counts(s->device, job, 1);
+    if (st != FE_OK) return srv_fail(st, fe_last_error());
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->status != FE_OK) return srv_fail(s->status, s->error.c_str());
     if (s->stop.load()) return srv_fail(FE_ERR_INVALID, "server is shutting down");

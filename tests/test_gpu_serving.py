@@ -63,3 +63,29 @@ def test_server_rejects_job_larger_than_budget(env):
     with pytest.raises(fe.FeError):
         srv.submit(fe.JobSpec(y, 10.0, 5, tau, gamma, data_term="idiv"), 0)
     srv.close()
+
+
+def test_server_validation_mode_rejects_bad_request_and_keeps_serving(env):
+    """FE_VALIDATE=1: a request with a NaN count is refused at submit; the
+    server keeps serving the others, bitwise as alone."""
+    import os
+    torch, fe, serving, prior = env
+    specs = _specs(fe, torch, 4, seed=9)
+    os.environ["FE_VALIDATE"] = "1"
+    try:
+        srv = serving.Server(prior, 256 << 20, iters_per_tick=6, max_active=16)
+        bad = specs[0].counts.clone()
+        bad[1, 2] = float("nan")
+        tau, gamma = step_size_for(7, 48)
+        with pytest.raises(fe.FeError):
+            srv.submit(fe.JobSpec(bad, 40.0, 10, tau, gamma, data_term="auto", peak=2.0), 99)
+        comps, outs, wall = serving.run_stream(srv, np.zeros(len(specs)), specs, timeout_s=120)
+        srv.close()
+    finally:
+        del os.environ["FE_VALIDATE"]
+    torch.cuda.synchronize()
+    assert sorted(c["tag"] for c in comps) == list(range(len(specs)))
+    for j, s in enumerate(specs):
+        (x1, _), = fe.denoise_jobs(prior, [s])
+        torch.cuda.synchronize()
+        assert torch.equal(outs[j][0], x1), j
