@@ -213,6 +213,10 @@ def make_jobs(specs):
         oa = s.out_anscombe
         if oa is None and s.want_anscombe:
             oa = torch.empty_like(c)
+        for t, name in ((out, "out"), (oa, "out_anscombe")):
+            if t is not None and (_device_f32(t, name).shape != c.shape
+                                  or t.device != c.device):
+                raise ValueError(name + " must match counts in shape and device")
         keep.append((c, out, oa))
         dt = _DATA[s.data_term] if isinstance(s.data_term, str) else int(s.data_term)
         pr = _PREC[s.precision] if isinstance(s.precision, str) else int(s.precision)

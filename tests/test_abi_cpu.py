@@ -121,3 +121,14 @@ def test_tuning_and_graph_calls_validate_before_device_work(lib):
     assert h.value is None
     assert lib.fe_graph_launch(None, None) == fe.FE_ERR_INVALID
     lib.fe_graph_destroy(None)  # NULL-safe
+
+
+def test_binding_rejects_host_or_malformed_tensors():
+    """The binding marshals device tensors only: host, non-contiguous,
+    non-float32 or non-2-D inputs are refused before the library is called."""
+    import torch
+    import paper_1609_05722_amd as fe
+    for bad in (torch.zeros(8, 8), torch.zeros(8, 8, dtype=torch.float64), torch.zeros(8),
+                torch.zeros(8, 16)[:, ::2]):
+        with pytest.raises(ValueError):
+            fe.make_jobs([fe.JobSpec(bad, 1.0, 1, 0.1, 0.5)])
