@@ -58,7 +58,25 @@ def build(verbose=False, jobs=4):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
+    build_c_demo(verbose)
     return LIB
+
+
+def build_c_demo(verbose=False):
+    """The plain C client of the ABI used by the tests (tests/c_abi_demo.c),
+    linked against libfe.so next to it: _build/c_abi_demo."""
+    src = os.path.join(ROOT, "tests", "c_abi_demo.c")
+    if not os.path.exists(src):
+        return None
+    exe = os.path.join(HERE, "_build", "c_abi_demo")
+    cmd = ["gcc", "-std=c11", "-O1", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), src, LIB,
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN/..",
+           "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return exe
 
 
 if __name__ == "__main__":
