@@ -88,7 +88,7 @@ typedef struct {
 
 /* One denoising job (one noisy image). */
 typedef struct {
-    int32_t height, width;  /* each >= r = (m - 1) / 2                     */
+    int32_t height, width;  /* each >= r = (m - 1) / 2; H * W < 2^31       */
     const float *counts;    /* DEVICE H*W, y >= 0, integer valued          */
     float *out;             /* DEVICE H*W, x_hat = I_C(u_hat); may be NULL */
     float *out_anscombe;    /* DEVICE H*W, u_hat (Anscombe domain) or NULL */

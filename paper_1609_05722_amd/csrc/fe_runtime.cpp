@@ -7,13 +7,13 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
-#include <fstream>
-#include <sstream>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -26,7 +26,7 @@ struct fe_ctx {
     std::vector<float> taps, alpha;  // host copies
     fe::DeviceBank bank;
     fe::FusedBank fused;             // matrix-core operand tables
-    mutable fe::TuneTable tune;      // measured tile heights (internally locked)
+    mutable fe::TuneTable tune;      // measured tile shapes (internally locked)
 };
 
 namespace {
