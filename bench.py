@@ -111,6 +111,28 @@ def cpu_baseline(args, k, a, job, tau, gamma):
                                      sample="64x64, peak 4, 24 5x5 filters, 100 iterations")}
 
 
+def cpu_all_images(args, k, a, jobs, tau, gamma):
+    """The oracle on every image of the FP32 baseline, on one thread and on
+    all of them: Mpixel-iter/s per (image peak, threads)."""
+    import oracle
+    full = len(os.sched_getaffinity(0))
+    out = {}
+    for j in jobs:
+        _, y = j.arrays()
+        for n_thr in (1, full):
+            oracle.set_threads(n_thr)
+            t0 = time.perf_counter()
+            oracle.denoise(y, k, a, j.lam, tau, gamma, args.cpu_iters, j.data_term)
+            dt = time.perf_counter() - t0
+            out["peak%g_cores%d" % (j.peak, n_thr)] = round(y.size * args.cpu_iters / dt / 1e6, 3)
+            print(json.dumps({"cpu_oracle": {"peak": j.peak, "cores": n_thr, "seconds": dt}}),
+                  file=sys.stderr, flush=True)
+    oracle.set_threads(full)
+    out["unit"] = "Mpixel-iter/s"
+    out["iterations"] = args.cpu_iters
+    return out
+
+
 def batch_report(fe, torch, prior, args, tau, gamma, log=None):
     """Uneven batch: 256 images with sides log-uniform on [128, 1024],
     peaks {1, 2, 4, 8}, 200 iterations each, all in one launch per
@@ -215,6 +237,9 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--iterations", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--cpu-all-images", action="store_true",
+                    help="also time the oracle on all four 512x512 images, on one and on "
+                         "all host threads (minutes of CPU work; off by default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
@@ -351,6 +376,9 @@ def main():
     if not args.no_cpu:
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
         result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)
+        if args.cpu_all_images:
+            result["cpu_baseline"]["all_images"] = cpu_all_images(args, k, a, cfg["jobs"],
+                                                                  tau, gamma)
     print(json.dumps(result), flush=True)
 
 
