@@ -74,6 +74,21 @@ MUTANTS = [
      "for (long p = 0; p < n; ++p) grad[p] += 0.0 * gd[p];", pins.grad_full_fd, 1e-3),
     ("idiv_energy_log", "t[p] = u[p] - v[p] * log(u[p]);", "t[p] = u[p] - log(u[p]);",
      pins.grad_full_fd, 1e-3),
+    ("bin3_zero_padding",
+     "s += y[sym_index(3 * i + a, H) * W + sym_index(3 * j + b, W)];",
+     "s += (3 * i + a < H && 3 * j + b < W) ? y[(3 * i + a) * W + 3 * j + b] : 0.0;",
+     pins.bin3_vs_padded, 0.5),
+    ("bin3_short_block", "for (int a = 0; a < 3; ++a)\n                for (int b = 0; b < 3; ++b)",
+     "for (int a = 0; a < 2; ++a)\n                for (int b = 0; b < 3; ++b)",
+     pins.bin3_vs_padded, 0.5),
+    ("upsample3_centre_offset", "double fy = (y - 1) / 3.0;", "double fy = y / 3.0;",
+     pins.upsample3_centres, 1e-6),
+    ("upsample3_no_division", "x[y * W + xx] = v / 9.0;", "x[y * W + xx] = v;",
+     pins.upsample3_centres, 1e-6),
+    ("upsample3_swapped_weights",
+     "((1.0 - wx) * xb[i0 * Wb + j0] + wx * xb[i0 * Wb + j1])",
+     "(wx * xb[i0 * Wb + j0] + (1.0 - wx) * xb[i0 * Wb + j1])",
+     pins.upsample3_vs_scipy, 1e-6),
 ]
 
 

@@ -36,6 +36,35 @@ def _prior(m=5, nf=6, seed=3):
 # ----------------------------------------------------------------------------
 class pins:
     @staticmethod
+    def bin3_vs_padded(H=10, W=14):
+        """Section 4 binning: 3 x 3 block sums of the symmetric extension to a
+        multiple of 3 (numpy's symmetric padding), ragged on both axes."""
+        y = np.random.default_rng(H * W).poisson(2.0, (H, W)).astype(np.float64)
+        Hb, Wb = (H + 2) // 3, (W + 2) // 3
+        e = np.pad(y, ((0, 3 * Hb - H), (0, 3 * Wb - W)), mode="symmetric")
+        return np.abs(oracle.bin3(y) - e.reshape(Hb, 3, Wb, 3).sum(axis=(1, 3))).max()
+
+    @staticmethod
+    def upsample3_vs_scipy(Hb=5, Wb=7, H=14, W=20):
+        """Bilinear upscaling of xb / 9 from the bin centres (3i + 1, 3j + 1),
+        coordinates clamped to the outermost centres, against scipy."""
+        from scipy.interpolate import RegularGridInterpolator
+        xb = np.random.default_rng(13).uniform(0, 50, (Hb, Wb))
+        f = RegularGridInterpolator((3 * np.arange(Hb) + 1.0, 3 * np.arange(Wb) + 1.0),
+                                    xb / 9.0)
+        yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+        pts = np.stack([np.clip(yy, 1, 3 * (Hb - 1) + 1), np.clip(xx, 1, 3 * (Wb - 1) + 1)],
+                       -1)
+        return np.abs(oracle.upsample3(xb, H, W) - f(pts)).max()
+
+    @staticmethod
+    def upsample3_centres():
+        """At a bin centre the upscaled value is that bin's estimate / 9."""
+        xb = np.random.default_rng(2).uniform(0, 9, (4, 5))
+        x = oracle.upsample3(xb, 12, 15)
+        return np.abs(x[1::3, 1::3] - xb / 9.0).max()
+
+    @staticmethod
     def anscombe_zero():
         """Section 3.2: a zero count maps to sqrt(3/2)."""
         g = _golden()["anscombe_zero_count"]["value"]
@@ -377,33 +406,17 @@ def test_idiv_energy_infinite_off_domain():
 # ---- binning variant -------------------------------------------------------
 @pytest.mark.parametrize("H,W", [(9, 12), (10, 11), (7, 8), (31, 17)])
 def test_bin3_matches_padded_block_sums(H, W):
-    """Bins equal block sums of numpy's symmetric padding to a multiple of 3."""
-    y = np.random.default_rng(H * W).poisson(2.0, (H, W)).astype(np.float64)
-    Hb, Wb = (H + 2) // 3, (W + 2) // 3
-    e = np.pad(y, ((0, 3 * Hb - H), (0, 3 * Wb - W)), mode="symmetric")
-    ref = e.reshape(Hb, 3, Wb, 3).sum(axis=(1, 3))
-    assert np.array_equal(oracle.bin3(y), ref)
+    assert pins.bin3_vs_padded(H, W) == 0.0
 
 
 def test_upsample3_is_bilinear_with_clamped_edges():
-    """Against scipy's regular-grid linear interpolation of xb / 9 with the
-    sample coordinates clamped to the outermost bin centres."""
-    from scipy.interpolate import RegularGridInterpolator
-    g = np.random.default_rng(13)
-    Hb, Wb, H, W = 5, 7, 14, 20
-    xb = g.uniform(0, 50, (Hb, Wb))
-    f = RegularGridInterpolator((3 * np.arange(Hb) + 1.0, 3 * np.arange(Wb) + 1.0), xb / 9.0)
-    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
-    pts = np.stack([np.clip(yy, 1, 3 * (Hb - 1) + 1), np.clip(xx, 1, 3 * (Wb - 1) + 1)], -1)
-    assert np.abs(oracle.upsample3(xb, H, W) - f(pts)).max() < 1e-12
+    assert pins.upsample3_vs_scipy() < 1e-12
 
 
 def test_upsample3_keeps_constants_and_centres():
     xb = np.full((4, 4), 27.0)
     assert np.abs(oracle.upsample3(xb, 12, 11) - 3.0).max() < 1e-14
-    xb = np.random.default_rng(2).uniform(0, 9, (4, 5))
-    x = oracle.upsample3(xb, 12, 15)
-    assert np.abs(x[1::3, 1::3] - xb / 9.0).max() < 1e-14
+    assert pins.upsample3_centres() < 1e-14
 
 
 def test_iterations_are_local():
