@@ -74,6 +74,10 @@ MUTANTS = [
      "for (long p = 0; p < n; ++p) grad[p] += 0.0 * gd[p];", pins.grad_full_fd, 1e-3),
     ("idiv_energy_log", "t[p] = u[p] - v[p] * log(u[p]);", "t[p] = u[p] - log(u[p]);",
      pins.grad_full_fd, 1e-3),
+    ("power_iteration_weights",
+     "for (long p = 0; p < n; ++p) z[(size_t)i * n + p] *= alpha[i];",
+     "for (long p = 0; p < n; ++p) z[(size_t)i * n + p] *= 1.0;",
+     pins.power_iteration_vs_eig, 1e-3),
     ("bin3_zero_padding",
      "s += y[sym_index(3 * i + a, H) * W + sym_index(3 * j + b, W)];",
      "s += (3 * i + a < H && 3 * j + b < W) ? y[(3 * i + a) * W + 3 * j + b] : 0.0;",

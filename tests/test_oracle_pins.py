@@ -36,6 +36,17 @@ def _prior(m=5, nf=6, seed=3):
 # ----------------------------------------------------------------------------
 class pins:
     @staticmethod
+    def power_iteration_vs_eig(H=8, W=8, m=5, nf=6):
+        """The step-size bound's lambda_max(sum_i alpha_i K_i^T K_i) from the
+        oracle's power iteration against the dense eigenvalue problem."""
+        k, a = _prior(m, nf)
+        Ks = brute.dense_bank(k, H, W)
+        A = sum(ai * K.T @ K for K, ai in zip(Ks, a))
+        lam = np.linalg.eigvalsh(A).max()
+        x0 = np.random.default_rng(1).standard_normal((H, W))
+        return abs(oracle.power_iteration(x0, k, a, 3000) - lam) / lam
+
+    @staticmethod
     def bin3_vs_padded(H=10, W=14):
         """Section 4 binning: 3 x 3 block sums of the symmetric extension to a
         multiple of 3 (numpy's symmetric padding), ragged on both axes."""
@@ -411,6 +422,11 @@ def test_bin3_matches_padded_block_sums(H, W):
 
 def test_upsample3_is_bilinear_with_clamped_edges():
     assert pins.upsample3_vs_scipy() < 1e-12
+
+
+def test_power_iteration_matches_dense_eigenvalue():
+    """The Lipschitz estimate behind tau (reading of Section 2.4)."""
+    assert pins.power_iteration_vs_eig() < 1e-8
 
 
 def test_upsample3_keeps_constants_and_centres():
