@@ -355,7 +355,17 @@ def main():
         "hbm_algorithmic_GBs": round(hbm_bytes_per_px_it() * px_per_launch
                                      / (launch_ms * 1e-3) / 1e9, 1),
     }
-    if not args.no_mixed:
+    def section(name, fn):
+        """An optional part of the line; a Python error in it is reported in
+        the line instead of losing the whole measurement."""
+        try:
+            result[name] = fn()
+        except Exception as exc:  # noqa: BLE001 - reported, not hidden
+            import traceback
+            traceback.print_exc()
+            result[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
+
+    def mixed_section():
         mixed = {}
         for prec in ("bf16", "fp16"):
             ms_p, launch_p, _, _ = measure(prec, args.steps, 1)
@@ -366,19 +376,29 @@ def main():
                            "launch_us": round(launch_p * 1e3, 2),
                            "achieved_TFLOPs": round(ach, 3),
                            "frac_of_mfma_peak": round(ach / MFMA16_PEAK_TFLOPS, 4)}
-        result["mixed_precision"] = mixed
-    if not args.no_batch:
-        result["batch"] = batch_report(fe, torch, prior, args, tau, gamma,
-                                       log=lambda t: print(t, file=sys.stderr, flush=True))
-    if not args.no_serving:
+        return mixed
+
+    def serving_section():
         from paper_1609_05722_amd.serving import serving_report
-        result["serving"] = serving_report(prior, args.serving_requests, (0.5, 0.9), "bf16")
-    if not args.no_cpu:
+        return serving_report(prior, args.serving_requests, (0.5, 0.9), "bf16")
+
+    def cpu_section():
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
-        result["cpu_baseline"] = cpu_baseline(args, k, a, job4, tau, gamma)
+        out = cpu_baseline(args, k, a, job4, tau, gamma)
         if args.cpu_all_images:
-            result["cpu_baseline"]["all_images"] = cpu_all_images(args, k, a, cfg["jobs"],
-                                                                  tau, gamma)
+            out["all_images"] = cpu_all_images(args, k, a, cfg["jobs"], tau, gamma)
+        return out
+
+    if not args.no_mixed:
+        section("mixed_precision", mixed_section)
+    if not args.no_batch:
+        section("batch", lambda: batch_report(fe, torch, prior, args, tau, gamma,
+                                              log=lambda t: print(t, file=sys.stderr,
+                                                                  flush=True)))
+    if not args.no_serving:
+        section("serving", serving_section)
+    if not args.no_cpu:
+        section("cpu_baseline", cpu_section)
     print(json.dumps(result), flush=True)
 
 
