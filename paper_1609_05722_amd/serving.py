@@ -18,7 +18,7 @@ import time
 
 import numpy as np
 
-from . import (FeError, JobSpec, _check, _Job, library, make_jobs)
+from . import FeError, JobSpec, _Job, library, make_jobs
 
 
 class _Cfg(ctypes.Structure):

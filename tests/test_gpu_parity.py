@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import make_prior, noisy_pair
+from synth import noisy_pair
 from synth.workloads import (IDIV, QUADRATIC, fp32_config, oracle_config,
                              prior_for, step_size_for)
 

@@ -1,7 +1,6 @@
 """The tile-height autotuner and the captured step sequence (HIP graph),
 both through the C ABI.  Neither may change a result: tuned, forced and
 replayed runs are compared bitwise with plain eager runs."""
-import numpy as np
 import pytest
 
 from synth import noisy_pair
