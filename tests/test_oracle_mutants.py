@@ -74,6 +74,10 @@ MUTANTS = [
      "for (long p = 0; p < n; ++p) grad[p] += 0.0 * gd[p];", pins.grad_full_fd, 1e-3),
     ("idiv_energy_log", "t[p] = u[p] - v[p] * log(u[p]);", "t[p] = u[p] - log(u[p]);",
      pins.grad_full_fd, 1e-3),
+    ("energy_log_argument", "log(1.0 + z * z)", "log(2.0 + z * z)",
+     pins.energy_prior_vs_dense, 1e-3),
+    ("quadratic_energy_half", "0.5 * d * d", "d * d",
+     pins.energy_quadratic_offset, 1e-3),
     ("power_iteration_weights",
      "for (long p = 0; p < n; ++p) z[(size_t)i * n + p] *= alpha[i];",
      "for (long p = 0; p < n; ++p) z[(size_t)i * n + p] *= 1.0;",

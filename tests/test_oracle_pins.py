@@ -36,6 +36,20 @@ def _prior(m=5, nf=6, seed=3):
 # ----------------------------------------------------------------------------
 class pins:
     @staticmethod
+    def energy_prior_vs_dense(H=8, W=8, m=5, nf=6):
+        """FoE energy (eq. 2.5, rho of eq. 2.6) against the dense matrices."""
+        k, a = _prior(m, nf)
+        u = np.random.default_rng(9).uniform(0.5, 3.0, (H, W))
+        ref = brute.energy_prior(u.ravel(), brute.dense_bank(k, H, W), a)
+        return abs(oracle.energy_prior(u, k, a) - ref) / abs(ref)
+
+    @staticmethod
+    def energy_quadratic_offset(H=6, W=7, lam=3.0, d=0.25):
+        """Quadratic data term (eq. 3.4) at u = v + d: lambda / 2 * N * d^2."""
+        v = np.random.default_rng(10).uniform(1.0, 4.0, (H, W))
+        return abs(oracle.energy_data(v + d, v, lam, 1) - 0.5 * lam * H * W * d * d)
+
+    @staticmethod
     def power_iteration_vs_eig(H=8, W=8, m=5, nf=6):
         """The step-size bound's lambda_max(sum_i alpha_i K_i^T K_i) from the
         oracle's power iteration against the dense eigenvalue problem."""
@@ -422,6 +436,14 @@ def test_bin3_matches_padded_block_sums(H, W):
 
 def test_upsample3_is_bilinear_with_clamped_edges():
     assert pins.upsample3_vs_scipy() < 1e-12
+
+
+def test_energy_prior_matches_dense():
+    assert pins.energy_prior_vs_dense() < 1e-12
+
+
+def test_quadratic_energy_closed_form():
+    assert pins.energy_quadratic_offset() < 1e-12
 
 
 def test_power_iteration_matches_dense_eigenvalue():
