@@ -63,14 +63,43 @@ def recorded_traffic(args):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(args, k, a, job, tau, gamma):
+def accuracy(gpu, uo, xo, clean, peak):
+    """Errors of the library's outputs against the FP64 oracle's on the same
+    image: max and RMS of x_hat and u_hat, the largest per-pixel relative
+    error |gpu - oracle| / max(|oracle|, 1), and the PSNR of x_hat against the
+    clean image (10 log10(peak^2 / MSE), count domain) minus the oracle's."""
+    def psnr(xh):
+        return 10.0 * np.log10(peak ** 2 / np.mean((xh - clean) ** 2))
+
+    p0 = psnr(xo)
+    out = {"oracle_psnr_db": round(float(p0), 4)}
+    for prec, (xg, ug) in gpu.items():
+        ex, eu = np.abs(xg - xo), np.abs(ug - uo)
+        rel = max(float(np.max(ex / np.maximum(np.abs(xo), 1.0))),
+                  float(np.max(eu / np.maximum(np.abs(uo), 1.0))))
+        out[prec] = {"max_abs_err_x": float("%.3e" % ex.max()),
+                     "rms_err_x": float("%.3e" % np.sqrt(np.mean(ex ** 2))),
+                     "max_abs_err_u": float("%.3e" % eu.max()),
+                     "rms_err_u": float("%.3e" % np.sqrt(np.mean(eu ** 2))),
+                     "max_rel_err": float("%.3e" % rel),
+                     "dpsnr_db": round(float(psnr(xg) - p0), 5)}
+    return out
+
+
+def cpu_baseline(args, k, a, job, tau, gamma, gpu=None):
+    """The FP64 oracle timed on the host cores.  gpu: the library's (x_hat,
+    u_hat) of the same job per precision; when the oracle runs the job's
+    own iteration count, their errors against its result are reported."""
     import oracle
     threads = oracle.set_threads(len(os.sched_getaffinity(0)))
-    _, y = job.arrays()
+    clean, y = job.arrays()
     its = args.cpu_iters
     t0 = time.perf_counter()
-    oracle.denoise(y, k, a, job.lam, tau, gamma, its, job.data_term)
+    uo, xo = oracle.denoise(y, k, a, job.lam, tau, gamma, its, job.data_term)
     dt = time.perf_counter() - t0
+    acc = None
+    if gpu and its == job.iterations:
+        acc = accuracy(gpu, uo, xo, clean, job.peak)
     px_it = job.height * job.width * its
     # the same oracle on one host thread, on a 256 x 256 crop for 20 iterations
     oracle.set_threads(1)
@@ -108,7 +137,8 @@ def cpu_baseline(args, k, a, job, tau, gamma):
                             "cores": 1, "seconds": dt1,
                             "sample": "256x256 crop of the same image, 20 iterations"},
             "oracle_size_case": dict(small_rates, unit="Mpixel-iter/s",
-                                     sample="64x64, peak 4, 24 5x5 filters, 100 iterations")}
+                                     sample="64x64, peak 4, 24 5x5 filters, 100 iterations"),
+            "accuracy": acc}
 
 
 def cpu_all_images(args, k, a, jobs, tau, gamma):
@@ -384,7 +414,17 @@ def main():
 
     def cpu_section():
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]
-        out = cpu_baseline(args, k, a, job4, tau, gamma)
+        # the library's outputs for the same image, one per precision
+        gpu = {}
+        c4 = counts[cfg["jobs"].index(job4)]
+        for prec in ("fp32",) + (() if args.no_mixed else ("bf16", "fp16")):
+            x4, u4 = fe.denoise(c4, prior, job4.lam, job4.iterations, tau, gamma,
+                                data_term=job4.data_term, peak=job4.peak, precision=prec,
+                                want_anscombe=True)
+            torch.cuda.synchronize()
+            gpu[prec] = (x4.cpu().numpy().astype(np.float64),
+                         u4.cpu().numpy().astype(np.float64))
+        out = cpu_baseline(args, k, a, job4, tau, gamma, gpu)
         if args.cpu_all_images:
             out["all_images"] = cpu_all_images(args, k, a, cfg["jobs"], tau, gamma)
         return out

@@ -34,7 +34,8 @@ struct FusedBank {
 // each run by a workgroup of `waves` waves.
 struct Plan {
     int tile_w = 0, tile_h = 0, waves = 0;
-    int njobs = 0, ntiles = 0;
+    int njobs = 0;
+    long ntiles = 0;
     std::vector<int> jobs_ntx, jobs_nty;
     size_t device_bytes() const;  // job table in the workspace
 };

@@ -43,6 +43,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cstring>
 #include <string>
@@ -58,6 +59,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // Global-memory float.  Pointers read out of the job table are generic;
@@ -67,6 +69,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(1))) float gfloat;
 // LDS quad: 16-byte reads through it compile to ds_read_b128.
 typedef __attribute__((address_space(3))) f32x4 lquad;
+typedef __attribute__((address_space(3))) u32x2 lpair;
 
 // Waves per workgroup: FP32 is built for 8 (every operand in registers,
 // two waves per SIMD) and 12 (adjoint tables in LDS, three per SIMD);
@@ -124,7 +127,7 @@ template <int M, typename Math>
 constexpr size_t lds_fixed_floats()
 {
     using G = Geo<M>;
-    return (size_t)Math::kNW * G::SROWS * G::SW +
+    return (size_t)Math::kNW * Math::kScratchFloats +
            (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * kQW + Math::kTabFloats;
 }
 
@@ -193,6 +196,8 @@ struct MathF32 {
     static constexpr int SA = odd_quads(NA), SL = odd_quads(NFB * 4);
     static constexpr int kTabFloats = LDS ? 64 * (SA + 2 * SL) : 0;
     static constexpr bool kPairTile = false;
+    static constexpr bool kGather = false;               // scatter form + collapse
+    static constexpr int kScratchFloats = G::SROWS * G::SW;  // C[px][tap] of one block
     static constexpr int RB = LDS ? 1 : NFB;             // register-resident copies
     float afwd[G::KF][NFB];
     float badj[RB][LDS ? 1 : 4][LDS ? 1 : G::NTB];
@@ -353,17 +358,30 @@ struct MathF32 {
 // ---------------------------------------------------------------------------
 // Block arithmetic, BF16 or FP16 operands (P), v_mfma_f32_16x16x32_*:
 // lane l supplies A[l % 16][8 (l/16) + e] and B[8 (l/16) + e][l % 16],
-// e = 0..7, as 8 packed values.  Tables (8 values of P per lane per slot):
-//   t0 forward A   [KS][NFB][64][8]   A[filter 16fb + l%16][tap 32s + 8(l/16) + e]
-//   t1 adjoint B   [KA][NTBP][64][8]  B[k = 8(l/16) + e][tap 16nb + l%16] * 2 alpha,
-//                  k standing for filter 16 (2s + e/4) + 4 (l/16) + e%4
+// e = 0..7, as 8 packed values; D[i][j] lands at lane j + 16 (i/4), item
+// i % 4.
+//
+// Forward as in FP32 (filters x pixels), all m^2 taps on the matrix cores.
+// Adjoint in gather form: psi, rounded to P, is stored per q-row in the
+// wave's scratch ([q-position][filter], zero beyond the q-row), and one
+// product per 16-pixel block yields the horizontal collapse directly,
+//   H[a][x] = sum_{b, f} psi_f(x - b + r) (2 alpha_f k_f(a, b)),
+// as D[16 px x 16 (a; only m used)] = A[16 px x K] B[K x 16 a] with
+// K = (b, group of 8 filters) slots of 8: the A operand of a lane is 8
+// consecutive filters of psi at one shifted pixel (one 16-byte LDS read).
+// Tables (8 values of P per lane per slot):
+//   t0 forward A   [KS][NFB][64][8]  A[filter 16fb + l%16][tap 32s + 8(l/16) + e]
+//   t1 adjoint B   [KG][64][8]       B[slot 4s + l/16 = (b, j), filter 8j + e][a = l%16]
+//                                    = 2 alpha_f k_f(a, b), slot = b * NJ + j
 template <int M, int NFB, typename P>
 struct MathP16 {
     using G = Geo<M>;
     static constexpr int kNW = kWavesP16;
     static constexpr bool kTwo = true;
+    static constexpr bool kGather = true;
     static constexpr int kTabFloats = 0;
     typedef P vec8 __attribute__((ext_vector_type(8)));
+    typedef P vec4 __attribute__((ext_vector_type(4)));
     // M = 7: k-step s covers tap rows 4s..4s+3, lane group g row 4s + g,
     // element e column e (8 x 8 padded; row 7 and column 7 weigh zero), so
     // a lane's 8 values are consecutive in the LDS tile.  Otherwise taps are
@@ -374,11 +392,22 @@ struct MathP16 {
     // of a k-step are then 4 aligned 32-bit words.
     static constexpr bool kPairTile = PAD;
     static constexpr int KS = PAD ? 2 : (G::T + 31) / 32;    // forward k-steps
-    static constexpr int KA = (NFB + 1) / 2;       // adjoint k-steps (32 filters)
-    static constexpr int NTBP = (G::T + 15) / 16;  // adjoint tap blocks
+    static constexpr int NJ = 2 * NFB;             // groups of 8 filters
+    static constexpr int KG = (NJ * M + 3) / 4;    // adjoint k-steps (4 slots each)
+    // psi scratch: q-positions -R .. QW + R - 1 (rows), PS values of P per
+    // row (16 NFB filters and 8 unused: a row stride of 8 (2 NFB + 1) bytes
+    // mod 32 words keeps the 16-byte reads of 8 consecutive lanes on
+    // distinct banks)
+    static constexpr int PS = 16 * NFB + 8;
+    static constexpr int PROWS = kQW + 2 * G::R;
+    static constexpr int kScratchFloats = PROWS * PS / 2;
+    // two forward accumulators in flight (not for 64 filters of 7 x 7,
+    // whose operand tables leave no room for them)
+    static constexpr bool kTwoAcc = !(M == 7 && NFB == 4);
     u32x4 afwd[KS][NFB];
-    u32x4 badj[KA][NTBP];
+    u32x4 bgat[KG];
     int boff[KS][PAD ? 1 : 8];
+    int aoff[KG];        // this lane's A operand of k-step s, block 0 (P elements)
     struct Acc {
         f32x4 z[NFB];
     };
@@ -404,9 +433,7 @@ struct MathP16 {
 #pragma unroll
             for (int fb = 0; fb < NFB; ++fb) afwd[s][fb] = fwd_tab[(s * NFB + fb) * 64 + lane];
 #pragma unroll
-        for (int s = 0; s < KA; ++s)
-#pragma unroll
-            for (int nb = 0; nb < NTBP; ++nb) badj[s][nb] = adj_tab[(s * NTBP + nb) * 64 + lane];
+        for (int s = 0; s < KG; ++s) bgat[s] = adj_tab[s * 64 + lane];
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if constexpr (PAD) {
@@ -419,6 +446,15 @@ struct MathP16 {
                     boff[s][e] = t < G::T ? (t / M) * G::US + (t % M) + p : p;
                 }
             }
+        }
+        // slot 4s + g = (b, j): psi of filters 8j.. at q-position p - b + R
+        // (row p - b + 2R); padding slots (zero B) read row p + R
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+            const int sg = 4 * s + g;
+            const bool ok = sg < NJ * M;
+            const int b = ok ? sg / NJ : G::R, j = ok ? sg % NJ : 0;
+            aoff[s] = (p - b + 2 * G::R) * PS + 8 * j;
         }
     }
 
@@ -443,36 +479,47 @@ struct MathP16 {
         }
     }
 
-    template <bool MASK>
-    __device__ __forceinline__ void adjoint(const Acc &a, bool inside, int p, int g,
-                                            float *Sw) const
+    // Influence of block k (FP32), rounded to P, into the psi scratch:
+    // filters 16fb + 4g .. + 3 of q-position 16k + p (8 bytes per fb); a
+    // q-position outside the image (inside = false) stores zeros.
+    __device__ __forceinline__ void store_psi(const Acc &a, bool inside, int p, int g,
+                                              unsigned short *Pw, int k) const
     {
-        vec8 phi[KA];
+        unsigned short *row = Pw + (16 * k + p + G::R) * PS + 4 * g;
 #pragma unroll
-        for (int s = 0; s < KA; ++s)
+        for (int fb = 0; fb < NFB; ++fb) {
+            vec4 v;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int fb = 2 * s + e / 4;
-                float ph = 0.0f;
-                if (fb < NFB) {
-                    const float zz = a.z[fb][e % 4];
-                    ph = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
-                    if (MASK) ph = inside ? ph : 0.0f;
-                }
-                phi[s][e] = (P)ph;
+            for (int i = 0; i < 4; ++i) {
+                const float zz = a.z[fb][i];
+                v[i] = (P)(zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f)));
             }
-        f32x4 c[NTBP];
+            u32x2 w = __builtin_bit_cast(u32x2, v);
+            w.x = inside ? w.x : 0u;
+            w.y = inside ? w.y : 0u;
+            *(volatile lpair *)(row + 16 * fb) = w;
+        }
+    }
+
+    // H[a][16k + 4g + jj] (a = p < M) of block k from the psi scratch.
+    __device__ __forceinline__ void gather(const unsigned short *Pw, float *Hs, int k, int p,
+                                           int g) const
+    {
+        const unsigned short *base = Pw + 16 * k * PS;
+        // all A operands are read before the first product (the reads are
+        // not volatile, so they may be issued back to back)
+        f32x4 w[KG];
 #pragma unroll
-        for (int nb = 0; nb < NTBP; ++nb) c[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < KG; ++s) w[s] = *(const lquad *)(base + aoff[s]);
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < KA; ++s)
-#pragma unroll
-            for (int nb = 0; nb < NTBP; ++nb)
-                c[nb] = mfma(phi[s], __builtin_bit_cast(vec8, badj[s][nb]), c[nb]);
-#pragma unroll
-        for (int nb = 0; nb < NTBP; ++nb)
-            if (16 * nb + 15 < G::T || 16 * nb + p < G::T)
-                *(f32x4 *)(Sw + (16 * nb + p) * G::SW + G::SPAD + 4 * g) = c[nb];
+        for (int s = 0; s < KG; ++s)
+            d = mfma(__builtin_bit_cast(vec8, w[s]), __builtin_bit_cast(vec8, bgat[s]), d);
+        // keep the reads ahead of the products (the scheduler would
+        // otherwise sink each read to its product and expose its latency)
+        __builtin_amdgcn_sched_group_barrier(0x0100, KG, 0);   // LDS reads
+        __builtin_amdgcn_sched_group_barrier(0x0008, KG, 0);   // MFMA
+        if (p < M) *(f32x4 *)(Hs + p * kQW + 16 * k + 4 * g) = d;
     }
 
     static __device__ __forceinline__ f32x4 mfma(vec8 a, vec8 b, f32x4 c)
@@ -486,10 +533,11 @@ struct MathP16 {
 
 template <int M, typename Math>
 __global__ __launch_bounds__(64 * Math::kNW)
+__attribute__((amdgpu_waves_per_eu(Math::kNW / 4, Math::kNW / 4)))
 void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                        const void *__restrict__ t0, const void *__restrict__ t1,
                        const void *__restrict__ t2, const void *__restrict__ t3,
-                       int iter, int ty_max)
+                       int iter, int ty_max, int tile0)
 {
     using G = Geo<M>;
     constexpr int R = G::R;
@@ -503,7 +551,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     // ---- locate the tile: jobs are sorted by tile_base --------------------
     int lo = 0, hi = njobs - 1;
-    const int bid = blockIdx.x;
+    const int bid = tile0 + (int)blockIdx.x;   // launches cover tiles tile0 ..
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (jobs[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
@@ -523,10 +571,11 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
-    float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // NW x SROWS x SW
-    float *Hr = S + (size_t)NW * G::SROWS * G::SW;         // HR x M x QW
+    float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // per-wave scratch
+    float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
     float *Tab = Hr + (size_t)HR * M * kQW;                // the policy's tables
-    float *Sw = S + (size_t)wave * G::SROWS * G::SW;
+    float *Sw = S + (size_t)wave * Math::kScratchFloats;
+    unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
 
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
     // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
@@ -547,8 +596,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     Math mth;
     mth.load(t0, t1, t2, t3, lane, Tab);
 
-    // ---- zero this wave's scratch (its pad columns stay zero) -------------
-    for (int i = lane; i < G::SROWS * G::SW; i += 64) Sw[i] = 0.0f;
+    // ---- zero this wave's scratch (its pad columns / rows stay zero) ------
+    for (int i = lane; i < Math::kScratchFloats; i += 64) Sw[i] = 0.0f;
 
     // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
     // (one more row and the two padding columns hold finite values that
@@ -586,11 +635,16 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // input vanishes off the image); blocks wholly inside skip the mask.
     auto adjoint = [&](int k, const Acc &acc) {
         const int q0 = x0 - R + 16 * k;
-        if (q0 >= 0 && q0 + 15 < W) {
-            mth.template adjoint<false>(acc, true, p, g, Sw);
-        } else {
+        if constexpr (Math::kGather) {
             const int qx = q0 + p;
-            mth.template adjoint<true>(acc, qx >= 0 && qx < W, p, g, Sw);
+            mth.store_psi(acc, qx >= 0 && qx < W, p, g, Pw, k);
+        } else {
+            if (q0 >= 0 && q0 + 15 < W) {
+                mth.template adjoint<false>(acc, true, p, g, Sw);
+            } else {
+                const int qx = q0 + p;
+                mth.template adjoint<true>(acc, qx >= 0 && qx < W, p, g, Sw);
+            }
         }
     };
     // ---- horizontal collapse of block k into the q-row's H slot -----------
@@ -689,21 +743,51 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         if (qr < nq && qy >= 0 && qy < H) {
             float *Hs = Hr + (size_t)(qr % HR) * M * kQW;
             Acc acc;
-            // software pipeline: the collapse of block k - 1 (LDS, VALU) is
-            // issued next to the forward MFMAs of block k
-            forward(qr, 0, acc);
-            adjoint(0, acc);
+            if constexpr (Math::kGather) {
+                // psi of every block into the scratch; block k's H needs psi
+                // of blocks k - 1 .. k + 1, so it follows psi of block k + 1.
+                // Branch-free, two accumulators: the forward products of
+                // block k + 1 are issued before the influence of block k.
+                // (one accumulator where two would not fit the registers)
+                constexpr bool two = Math::kTwoAcc;
+                Acc acc1;
+                Acc &accb = two ? acc1 : acc;
+                forward(qr, 0, acc);
+                if (two) forward(qr, 1, accb);
+                adjoint(0, acc);
+                if (!two) forward(qr, 1, accb);
+                if (two) forward(qr, 2, acc);
+                adjoint(1, accb);
+                lds_order();
+                mth.gather(Pw, Hs, 0, p, g);
+                if (!two) forward(qr, 2, acc);
+                if (two) forward(qr, 3, accb);
+                adjoint(2, acc);
+                lds_order();
+                mth.gather(Pw, Hs, 1, p, g);
+                if (!two) forward(qr, 3, accb);
+                adjoint(3, accb);
+                lds_order();
+                mth.gather(Pw, Hs, 2, p, g);
+                mth.gather(Pw, Hs, 3, p, g);
+                lds_order();
+            } else {
+                // software pipeline: the collapse of block k - 1 (LDS, VALU)
+                // is issued next to the forward MFMAs of block k
+                forward(qr, 0, acc);
+                adjoint(0, acc);
 #pragma unroll
-            for (int k = 1; k < kQB; ++k) {
+                for (int k = 1; k < kQB; ++k) {
+                    lds_order();
+                    forward(qr, k, acc);
+                    collapse(Hs, k - 1);
+                    lds_order();
+                    adjoint(k, acc);
+                }
                 lds_order();
-                forward(qr, k, acc);
-                collapse(Hs, k - 1);
+                collapse(Hs, kQB - 1);
                 lds_order();
-                adjoint(k, acc);
             }
-            lds_order();
-            collapse(Hs, kQB - 1);
-            lds_order();
         }
     };
 
@@ -736,6 +820,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 // Job table upload through kernel arguments (no host-to-device copy, so the
 // call stays asynchronous and capturable).
 constexpr int kChunk = 32;
+constexpr int kMaxLaunchTiles = 1 << 21;   // x 1024 threads at most = 2^31 work-items
 struct JobChunk {
     int first, count;
     JobDesc d[kChunk];
@@ -750,8 +835,8 @@ __global__ void write_jobs_kernel(JobChunk c, JobDesc *dst)
 int nfb_for(int nf) { return (nf + 15) / 16; }
 
 template <int M, typename Math>
-hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, int ntiles,
-                       int iter, int ty_max, hipStream_t s)
+hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, int nblocks,
+                       int tile0, int iter, int ty_max, hipStream_t s)
 {
     constexpr int NW = Math::kNW;
     if (ty_max > rows_limit<M, Math>()) return hipErrorInvalidValue;
@@ -769,8 +854,9 @@ hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, 
         if (e != hipSuccess) return e;
         attr_set.fetch_or(bit, std::memory_order_release);
     }
-    fused_step_kernel<M, Math><<<ntiles, 64 * NW, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
-                                                               tabs[2], tabs[3], iter, ty_max);
+    fused_step_kernel<M, Math><<<nblocks, 64 * NW, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
+                                                                tabs[2], tabs[3], iter, ty_max,
+                                                                tile0);
     return hipGetLastError();
 }
 
@@ -781,23 +867,23 @@ constexpr bool f32_lds_built() { return !(M == 7 && NFB == 4); }
 
 template <int M, int NFB>
 hipError_t launch_prec(int prec, int nw, const FusedBank &b, const JobDesc *jobs, int njobs,
-                       int ntiles, int iter, int ty_max, hipStream_t s)
+                       int nblocks, int tile0, int iter, int ty_max, hipStream_t s)
 {
     if (prec == FE_PREC_BF16) {
         const void *t[4] = {b.bf_fwd, b.bf_adj, nullptr, nullptr};
-        return launch_step<M, MathP16<M, NFB, __bf16>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+        return launch_step<M, MathP16<M, NFB, __bf16>>(t, jobs, njobs, nblocks, tile0, iter, ty_max, s);
     }
     if (prec == FE_PREC_FP16) {
         const void *t[4] = {b.h_fwd, b.h_adj, nullptr, nullptr};
-        return launch_step<M, MathP16<M, NFB, _Float16>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+        return launch_step<M, MathP16<M, NFB, _Float16>>(t, jobs, njobs, nblocks, tile0, iter, ty_max, s);
     }
     const void *t[4] = {b.fwd, b.adj, b.lastf, b.lasta};
     if (nw == 12) {
         if constexpr (f32_lds_built<M, NFB>())
-            return launch_step<M, MathF32<M, NFB, true>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+            return launch_step<M, MathF32<M, NFB, true>>(t, jobs, njobs, nblocks, tile0, iter, ty_max, s);
         return hipErrorInvalidValue;
     }
-    return launch_step<M, MathF32<M, NFB, false>>(t, jobs, njobs, ntiles, iter, ty_max, s);
+    return launch_step<M, MathF32<M, NFB, false>>(t, jobs, njobs, nblocks, tile0, iter, ty_max, s);
 }
 
 // Tallest tile of a variant (0 if the variant is not built).
@@ -816,10 +902,10 @@ int rows_prec(int prec, int nw)
 }
 
 hipError_t launch_any(int prec, int nw, const FusedBank &b, const JobDesc *jobs, int njobs,
-                      int ntiles, int iter, int ty_max, hipStream_t s)
+                      int nblocks, int tile0, int iter, int ty_max, hipStream_t s)
 {
 #define FE_STEP(MM, NB) \
-    return launch_prec<MM, NB>(prec, nw, b, jobs, njobs, ntiles, iter, ty_max, s)
+    return launch_prec<MM, NB>(prec, nw, b, jobs, njobs, nblocks, tile0, iter, ty_max, s)
     switch (b.m * 10 + b.nfb) {
     case 31: FE_STEP(3, 1);
     case 32: FE_STEP(3, 2);
@@ -888,8 +974,8 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
                 lasta[(fb * 4 + j) * 64 + l] = a2(f) * tap(f, T - 1);
             }
     // BF16 / FP16 operands (16x16x32 lane layout; see MathP16)
-    const int KS = m == 7 ? 2 : (T + 31) / 32, KA = (NFB + 1) / 2, NTBP = (T + 15) / 16;
-    std::vector<float> pf((size_t)KS * NFB * 64 * 8), pa((size_t)KA * NTBP * 64 * 8);
+    const int KS = m == 7 ? 2 : (T + 31) / 32, NJ = 2 * NFB, KG = (NJ * m + 3) / 4;
+    std::vector<float> pf((size_t)KS * NFB * 64 * 8), pa((size_t)KG * 64 * 8);
     for (int s = 0; s < KS; ++s)
         for (int fb = 0; fb < NFB; ++fb)
             for (int l = 0; l < 64; ++l)
@@ -899,15 +985,15 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
                                       ? tap(fb * 16 + (l & 15), (4 * s + (l >> 4)) * 7 + e)
                                       : 0.0f)
                                : tap(fb * 16 + (l & 15), 32 * s + 8 * (l >> 4) + e);
-    for (int s = 0; s < KA; ++s)
-        for (int nb = 0; nb < NTBP; ++nb)
-            for (int l = 0; l < 64; ++l)
-                for (int e = 0; e < 8; ++e) {
-                    const int fb = 2 * s + e / 4;
-                    const int f = 16 * fb + 4 * (l >> 4) + (e & 3), t = 16 * nb + (l & 15);
-                    pa[((s * NTBP + nb) * 64 + l) * 8 + e] =
-                        (fb < NFB && t < T) ? a2(f) * tap(f, t) : 0.0f;
-                }
+    for (int s = 0; s < KG; ++s)
+        for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+                // B[slot (b, j), filter 8j + e][a]: slot 4s + l/16 = b * NJ + j
+                const int sg = 4 * s + (l >> 4), a = l & 15;
+                const int b = sg / NJ, f = 8 * (sg % NJ) + e;
+                pa[((size_t)s * 64 + l) * 8 + e] =
+                    (sg < NJ * m && a < m) ? a2(f) * tap(f, a * m + b) : 0.0f;
+            }
     std::vector<uint16_t> bff(pf.size()), bfa(pa.size()), hf(pf.size()), ha(pa.size());
     for (size_t i = 0; i < pf.size(); ++i) {
         bff[i] = bf16_bits(pf[i]);
@@ -1091,7 +1177,7 @@ void make_plan(const FusedBank &bank, int prec, const AdvanceItem *items, int n,
         if (items[i].count <= 0) continue;   // contributes no tiles
         plan->jobs_ntx[i] = (items[i].job->width + TX - 1) / TX;
         plan->jobs_nty[i] = (items[i].job->height + best_ty - 1) / best_ty;
-        plan->ntiles += plan->jobs_ntx[i] * plan->jobs_nty[i];
+        plan->ntiles += (long)plan->jobs_ntx[i] * plan->jobs_nty[i];
     }
 }
 
@@ -1118,6 +1204,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         if (ch.waves <= 0 || max_tile_rows(bank, prec, ch.waves) <= 0)
             ch.waves = bank_default_waves(bank, prec);
         make_plan(bank, prec, grp.data(), gn, &plan, ch.waves, ch.ty);
+        if (plan.ntiles > INT_MAX) return hipErrorInvalidValue;   // tile indices are ints
         JobDesc *dj = table + slot;
         slot += gn;
         int max_it = 0, base = 0;
@@ -1153,10 +1240,15 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        for (int it = 0; it < max_it; ++it) {
-            hipError_t e = launch_any(prec, plan.waves, bank, dj, gn, plan.ntiles, it, plan.tile_h, s);
-            if (e != hipSuccess) return e;
-        }
+        // a launch covers at most kMaxLaunchTiles workgroups (its work-item
+        // count stays below 2^31)
+        for (int it = 0; it < max_it; ++it)
+            for (long t0 = 0; t0 < plan.ntiles; t0 += kMaxLaunchTiles) {
+                const int nb = (int)std::min<long>(kMaxLaunchTiles, plan.ntiles - t0);
+                hipError_t e = launch_any(prec, plan.waves, bank, dj, gn, nb, (int)t0, it,
+                                          plan.tile_h, s);
+                if (e != hipSuccess) return e;
+            }
     }
     return hipSuccess;
 }

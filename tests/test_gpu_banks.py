@@ -1,6 +1,6 @@
 """Every built filter-bank shape through the C ABI against the FP64 oracle:
 filter sides 3, 5 and 7 with 1, 2, 3 and 4 blocks of 16 filters (zero-padded
-inside the library), FP32 and BF16 contractions.  Banks beyond the paper's
+inside the library), FP32, BF16 and FP16 contractions.  Banks beyond the paper's
 DCT construction (more filters than m*m - 1 zero-mean atoms) are seeded
 random zero-mean filters; the step size comes from the oracle's power
 iteration for each bank."""
@@ -67,19 +67,26 @@ def test_bank_shapes_fp32(fe, torch, m, nf):
             assert np.max(np.abs(g - o) / np.maximum(np.abs(o), 1.0)) <= TOL
 
 
-@pytest.mark.parametrize("m,nf", [(3, 8), (5, 40), (7, 64)])
-def test_bank_shapes_bf16(fe, torch, m, nf):
-    """BF16 operands: within the reduced-precision bound of the parity tests
-    (operand rounding of 8 significant bits) of the FP64 oracle."""
+# Reduced-precision bound on u_hat after 20 iterations: operand rounding to
+# 8 (BF16) or 11 (FP16) significant bits on O(1) responses.
+_P16_TOL = {"bf16": 5e-2, "fp16": 1e-2}
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("m,nf", [(3, 8), (3, 20), (3, 64), (5, 16), (5, 24), (5, 40),
+                                  (7, 20), (7, 48), (7, 64)])
+def test_bank_shapes_reduced_precision(fe, torch, m, nf, precision):
+    """BF16 / FP16 operands, every filter side with 1 to 4 blocks of 16
+    filters: within the reduced-precision bound of the FP64 oracle."""
     k, a = _bank(m, nf, 300 + 10 * m + nf)
     tau, gamma = _step(k, a)
     prior = fe.Prior(k, a)
     _, y = noisy_pair(51 + nf, 61 + m, 70, 90, 2.0)
     x, u = fe.denoise(torch.from_numpy(y).cuda(), prior, 40.0, 20, float(tau), float(gamma),
-                      data_term=IDIV, precision="bf16", want_anscombe=True)
+                      data_term=IDIV, precision=precision, want_anscombe=True)
     torch.cuda.synchronize()
     uo, _ = oracle.denoise(y, k, a, np.float32(40.0), tau, gamma, 20, IDIV)
     err = np.abs(u.cpu().numpy().astype(np.float64) - uo)
-    print("bank %dx%d x %d bf16: max %.2e rms %.2e" % (m, m, nf, err.max(),
-                                                      np.sqrt(np.mean(err ** 2))), flush=True)
-    assert err.max() <= 5e-2
+    print("bank %dx%d x %d %s: max %.2e rms %.2e" % (m, m, nf, precision, err.max(),
+                                                    np.sqrt(np.mean(err ** 2))), flush=True)
+    assert err.max() <= _P16_TOL[precision]
