@@ -197,6 +197,8 @@ struct MathF32 {
     static constexpr int kTabFloats = LDS ? 64 * (SA + 2 * SL) : 0;
     static constexpr bool kPairTile = false;
     static constexpr bool kGather = false;               // scatter form + collapse
+    // u tile rows streamed during the steps (registers allow it with 8 waves)
+    static constexpr bool kStreamU = !LDS;
     static constexpr int kScratchFloats = G::SROWS * G::SW;  // C[px][tap] of one block
     static constexpr int RB = LDS ? 1 : NFB;             // register-resident copies
     float afwd[G::KF][NFB];
@@ -404,6 +406,7 @@ struct MathP16 {
     // two forward accumulators in flight (not for 64 filters of 7 x 7,
     // whose operand tables leave no room for them)
     static constexpr bool kTwoAcc = !(M == 7 && NFB == 4);
+    static constexpr bool kStreamU = kTwoAcc;   // u tile rows streamed during the steps
     u32x4 afwd[KS][NFB];
     u32x4 bgat[KG];
     int boff[KS][PAD ? 1 : 8];
@@ -601,9 +604,16 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
     // (one more row and the two padding columns hold finite values that
-    // zero-weight taps of the padded BF16/FP16 layout may read)
+    // zero-weight taps of the padded BF16/FP16 layout may read).  Step st
+    // reads tile rows below (st + 1) NW + 2R + 1.  Where the registers allow
+    // (Math::kStreamU), the prologue loads the rows of step 0 and during step
+    // st wave w fetches tile row (st + 1) NW + 2R + 1 + w (loads issued at
+    // the start of the step, the row stored to LDS before its first
+    // barrier); otherwise the prologue loads the whole tile.
     const int urows = ty + 4 * R + G::UROWS_EXTRA;
-    for (int i = threadIdx.x; i < urows * G::US; i += 64 * NW) {
+    constexpr int kURow0 = NW + 2 * R + G::UROWS_EXTRA;   // rows step 0 reads
+    const int urows0 = Math::kStreamU ? min(urows, kURow0) : urows;
+    for (int i = threadIdx.x; i < urows0 * G::US; i += 64 * NW) {
         const int ur = i / G::US, uc = i - ur * G::US;
         const int yy = sym_clamp(y0 - 2 * R + ur, H);
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
@@ -614,6 +624,36 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             U[ur * G::US + uc] = ucur[(long)yy * W + xx];
         }
     }
+    // the row a wave fetches: columns lane and 64 + lane (lane < US - 64),
+    // both values of each pair for the pair tile
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    float uf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto u_fetch = [&](int st) {
+        const int ur = (st + 1) * NW + 2 * R + G::UROWS_EXTRA + wv;
+        if (Math::kStreamU && ur < urows) {
+            const gfloat *row = ucur + (long)sym_clamp(y0 - 2 * R + ur, H) * W;
+            const int c0 = x0 - 2 * R + lane;
+            uf[0] = row[sym_clamp(c0, W)];
+            if constexpr (Math::kPairTile) uf[1] = row[sym_clamp(c0 + 1, W)];
+            if (lane < G::US - 64) {
+                uf[2] = row[sym_clamp(c0 + 64, W)];
+                if constexpr (Math::kPairTile) uf[3] = row[sym_clamp(c0 + 65, W)];
+            }
+        }
+    };
+    auto u_store = [&](int st) {
+        const int ur = (st + 1) * NW + 2 * R + G::UROWS_EXTRA + wv;
+        if (Math::kStreamU && ur < urows) {
+            float *dst = U + ur * G::US + lane;
+            if constexpr (Math::kPairTile) {
+                dst[0] = Math::pack_pair(uf[0], uf[1]);
+                if (lane < G::US - 64) dst[64] = Math::pack_pair(uf[2], uf[3]);
+            } else {
+                dst[0] = uf[0];
+                if (lane < G::US - 64) dst[64] = uf[2];
+            }
+        }
+    };
     Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
     // Every global load of the prologue (operand tables, u tile) has landed:
     // said explicitly, so that the compiler's wait counting does not carry
@@ -796,7 +836,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         // q-rows are now complete, barrier (the ring needs NW + 2R slots).
         for (int st = 0; st < nsteps; ++st) {
             prefetch(st);
+            u_fetch(st);
             qrow(st);
+            u_store(st);
             lds_barrier();
             finalize(st);
             lds_barrier();
@@ -810,7 +852,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             if (st > 0) finalize(st - 1);
             if (st < nsteps) {
                 prefetch(st);
+                u_fetch(st);
                 qrow(st);
+                u_store(st);
             }
             lds_barrier();
         }
