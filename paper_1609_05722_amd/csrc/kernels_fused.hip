@@ -128,7 +128,7 @@ constexpr size_t lds_fixed_floats()
 {
     using G = Geo<M>;
     return (size_t)Math::kNW * Math::kScratchFloats +
-           (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * kQW + Math::kTabFloats;
+           (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * Math::kHS + Math::kTabFloats;
 }
 
 template <int M, typename Math>
@@ -197,6 +197,7 @@ struct MathF32 {
     static constexpr int kTabFloats = LDS ? 64 * (SA + 2 * SL) : 0;
     static constexpr bool kPairTile = false;
     static constexpr bool kGather = false;               // scatter form + collapse
+    static constexpr int kHS = kQW;                      // H row stride (floats)
     // u tile rows streamed during the steps (registers allow it with 8 waves)
     static constexpr bool kStreamU = !LDS;
     static constexpr int kScratchFloats = G::SROWS * G::SW;  // C[px][tap] of one block
@@ -403,6 +404,9 @@ struct MathP16 {
     static constexpr int PS = 16 * NFB + 8;
     static constexpr int PROWS = kQW + 2 * G::R;
     static constexpr int kScratchFloats = PROWS * PS / 2;
+    // H row stride: 4 floats more than a q-row, so that the 16-byte stores of
+    // the m rows a of one block start on distinct banks
+    static constexpr int kHS = kQW + 4;
     // two forward accumulators in flight (not for 64 filters of 7 x 7,
     // whose operand tables leave no room for them)
     static constexpr bool kTwoAcc = !(M == 7 && NFB == 4);
@@ -522,7 +526,7 @@ struct MathP16 {
         // otherwise sink each read to its product and expose its latency)
         __builtin_amdgcn_sched_group_barrier(0x0100, KG, 0);   // LDS reads
         __builtin_amdgcn_sched_group_barrier(0x0008, KG, 0);   // MFMA
-        if (p < M) *(f32x4 *)(Hs + p * kQW + 16 * k + 4 * g) = d;
+        if (p < M) *(f32x4 *)(Hs + p * kHS + 16 * k + 4 * g) = d;
     }
 
     static __device__ __forceinline__ f32x4 mfma(vec8 a, vec8 b, f32x4 c)
@@ -576,7 +580,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *U = lds;                                        // (ty_max + 4R) x US
     float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // per-wave scratch
     float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
-    float *Tab = Hr + (size_t)HR * M * kQW;                // the policy's tables
+    float *Tab = Hr + (size_t)HR * M * Math::kHS;          // the policy's tables
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
     unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
 
@@ -593,7 +597,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int a = ok ? task / G::XSPAN : 0;
         const int xr = ok ? task - a * G::XSPAN - R : 0;
         sbase[rr] = (a * M) * G::SW + G::SPAD + xr + R;
-        hoff[rr] = a * kQW + xr;
+        hoff[rr] = a * Math::kHS + xr;
         xrr[rr] = ok ? xr : -1000;
     }
     Math mth;
@@ -749,7 +753,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 ok[a] = qyy >= 0 && qyy < H;
                 int q = ok[a] ? qyy - (y0 - R) : 0;
                 q = q >= HR ? q % HR : q;
-                const float *h = Hr + (size_t)q * M * kQW + a * kQW;
+                const float *h = Hr + (size_t)q * M * Math::kHS + a * Math::kHS;
                 vh[a] = h[hx];
                 vl[a] = h[hgl];
                 vr[a] = h[hgr];
@@ -781,7 +785,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int qr = st * NW + wave;
         const int qy = y0 - R + qr;
         if (qr < nq && qy >= 0 && qy < H) {
-            float *Hs = Hr + (size_t)(qr % HR) * M * kQW;
+            float *Hs = Hr + (size_t)(qr % HR) * M * Math::kHS;
             Acc acc;
             if constexpr (Math::kGather) {
                 // psi of every block into the scratch; block k's H needs psi
