@@ -135,7 +135,7 @@ template <int M, typename Math>
 size_t lds_bytes(int ty_max)
 {
     using G = Geo<M>;
-    return sizeof(float) * ((size_t)(ty_max + 4 * G::R + G::UROWS_EXTRA) * G::US +
+    return sizeof(float) * ((size_t)(ty_max + 4 * G::R + G::UROWS_EXTRA) * Math::kUS +
                             lds_fixed_floats<M, Math>());
 }
 
@@ -144,7 +144,7 @@ template <int M, typename Math>
 constexpr int rows_limit()
 {
     using G = Geo<M>;
-    const long rows = ((long)kLdsFloats - (long)lds_fixed_floats<M, Math>()) / G::US -
+    const long rows = ((long)kLdsFloats - (long)lds_fixed_floats<M, Math>()) / Math::kUS -
                       (4 * G::R + G::UROWS_EXTRA);
     return rows < kMaxTileRows ? (int)rows : kMaxTileRows;
 }
@@ -198,6 +198,7 @@ struct MathF32 {
     static constexpr bool kPairTile = false;
     static constexpr bool kGather = false;               // scatter form + collapse
     static constexpr int kHS = kQW;                      // H row stride (floats)
+    static constexpr int kUS = G::US;                    // u tile row stride (floats)
     // u tile rows streamed during the steps (registers allow it with 8 waves)
     static constexpr bool kStreamU = !LDS;
     static constexpr int kScratchFloats = G::SROWS * G::SW;  // C[px][tap] of one block
@@ -264,9 +265,9 @@ struct MathF32 {
 #pragma unroll
         for (int s = 0; s < G::KF; ++s) {
             const int t = 4 * s + g;
-            boff[s] = (t / M) * G::US + (t % M) + p;
+            boff[s] = (t / M) * kUS + (t % M) + p;
         }
-        loff = (M - 1) * G::US + (M - 1) + p;
+        loff = (M - 1) * kUS + (M - 1) + p;
         perm16 = (lane ^ 16) << 2;
         perm32 = (lane ^ 32) << 2;
     }
@@ -407,6 +408,10 @@ struct MathP16 {
     // H row stride: 4 floats more than a q-row, so that the 16-byte stores of
     // the m rows a of one block start on distinct banks
     static constexpr int kHS = kQW + 4;
+    // u tile row stride: 16 mod 32 floats, so that the 4-byte reads of the
+    // four lane groups (tap rows 4s + g) fall on disjoint banks
+    static constexpr int kUS = 80;
+    static_assert(kUS >= G::UC + 2, "u tile row too short");
     // two forward accumulators in flight (not for 64 filters of 7 x 7,
     // whose operand tables leave no room for them)
     static constexpr bool kTwoAcc = !(M == 7 && NFB == 4);
@@ -444,13 +449,13 @@ struct MathP16 {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if constexpr (PAD) {
-                boff[s][0] = (4 * s + g) * G::US + p;
+                boff[s][0] = (4 * s + g) * kUS + p;
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int t = 32 * s + 8 * g + e;
                     // padded taps read tap 0 (finite; its weight is zero)
-                    boff[s][e] = t < G::T ? (t / M) * G::US + (t % M) + p : p;
+                    boff[s][e] = t < G::T ? (t / M) * kUS + (t % M) + p : p;
                 }
             }
         }
@@ -578,7 +583,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const gfloat *counts = (const gfloat *)J.counts;
 
     float *U = lds;                                        // (ty_max + 4R) x US
-    float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * G::US;  // per-wave scratch
+    float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * Math::kUS;  // per-wave scratch
     float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
     float *Tab = Hr + (size_t)HR * M * Math::kHS;          // the policy's tables
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
@@ -617,15 +622,15 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int urows = ty + 4 * R + G::UROWS_EXTRA;
     constexpr int kURow0 = NW + 2 * R + G::UROWS_EXTRA;   // rows step 0 reads
     const int urows0 = Math::kStreamU ? min(urows, kURow0) : urows;
-    for (int i = threadIdx.x; i < urows0 * G::US; i += 64 * NW) {
-        const int ur = i / G::US, uc = i - ur * G::US;
+    for (int i = threadIdx.x; i < urows0 * Math::kUS; i += 64 * NW) {
+        const int ur = i / Math::kUS, uc = i - ur * Math::kUS;
         const int yy = sym_clamp(y0 - 2 * R + ur, H);
         const int xx = sym_clamp(x0 - 2 * R + uc, W);
         if constexpr (Math::kPairTile) {
             const int xx1 = sym_clamp(x0 - 2 * R + uc + 1, W);
-            U[ur * G::US + uc] = Math::pack_pair(ucur[(long)yy * W + xx], ucur[(long)yy * W + xx1]);
+            U[ur * Math::kUS + uc] = Math::pack_pair(ucur[(long)yy * W + xx], ucur[(long)yy * W + xx1]);
         } else {
-            U[ur * G::US + uc] = ucur[(long)yy * W + xx];
+            U[ur * Math::kUS + uc] = ucur[(long)yy * W + xx];
         }
     }
     // the row a wave fetches: columns lane and 64 + lane (lane < US - 64),
@@ -639,7 +644,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             const int c0 = x0 - 2 * R + lane;
             uf[0] = row[sym_clamp(c0, W)];
             if constexpr (Math::kPairTile) uf[1] = row[sym_clamp(c0 + 1, W)];
-            if (lane < G::US - 64) {
+            if (lane < Math::kUS - 64) {
                 uf[2] = row[sym_clamp(c0 + 64, W)];
                 if constexpr (Math::kPairTile) uf[3] = row[sym_clamp(c0 + 65, W)];
             }
@@ -648,13 +653,13 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     auto u_store = [&](int st) {
         const int ur = (st + 1) * NW + 2 * R + G::UROWS_EXTRA + wv;
         if (Math::kStreamU && ur < urows) {
-            float *dst = U + ur * G::US + lane;
+            float *dst = U + ur * Math::kUS + lane;
             if constexpr (Math::kPairTile) {
                 dst[0] = Math::pack_pair(uf[0], uf[1]);
-                if (lane < G::US - 64) dst[64] = Math::pack_pair(uf[2], uf[3]);
+                if (lane < Math::kUS - 64) dst[64] = Math::pack_pair(uf[2], uf[3]);
             } else {
                 dst[0] = uf[0];
-                if (lane < G::US - 64) dst[64] = uf[2];
+                if (lane < Math::kUS - 64) dst[64] = uf[2];
             }
         }
     };
@@ -672,7 +677,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     using Acc = typename Math::Acc;
     // ---- one 16-pixel block: forward bank (matrix cores) ------------------
     auto forward = [&](int qr, int k, Acc &acc) {
-        mth.forward(U + qr * G::US + 16 * k, acc);
+        mth.forward(U + qr * Math::kUS + 16 * k, acc);
     };
     // ---- influence, adjoint bank, tap contributions into the scratch ------
     // Pixels of block k outside the image carry psi = 0 (the adjoint's
@@ -776,7 +781,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         if (lane >= tx) return;
         float uc;
         if constexpr (Math::kPairTile) uc = pf_u;
-        else uc = U[(orow + 2 * R) * G::US + lane + 2 * R];
+        else uc = U[(orow + 2 * R) * Math::kUS + lane + 2 * R];
         const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
         uprev[(long)y * W + x] = prox(ut, anscombe(pf_y), J.tl, J.data_term);
     };

@@ -35,8 +35,8 @@ static void limits()
     const fe::FusedBank b7 = bank(7, 48);
     CHECK(fe::max_tile_rows(b7, FE_PREC_FP32, 8) == fe::kMaxTileRows);
     CHECK(fe::max_tile_rows(b7, FE_PREC_FP32, 12) == 96);
-    CHECK(fe::max_tile_rows(b7, FE_PREC_BF16, 12) == 110);
-    CHECK(fe::max_tile_rows(b7, FE_PREC_FP16, 12) == 110);
+    CHECK(fe::max_tile_rows(b7, FE_PREC_BF16, 12) == 97);
+    CHECK(fe::max_tile_rows(b7, FE_PREC_FP16, 12) == 97);
     CHECK(fe::max_tile_rows(b7, FE_PREC_BF16, 8) == 0);     // not built
     CHECK(fe::max_tile_rows(b7, FE_PREC_FP32, 10) == 0);
     // 64 filters of 7 x 7 do not fit three waves per SIMD in FP32

@@ -100,10 +100,10 @@ def test_autotune_and_forced_heights_are_bitwise(fe, torch, tmp_path):
         assert int(nw) in ((8, 12) if key.startswith("p0") else (12,)), ln
     # every variant and height gives the same bits: 8 or 12 waves for FP32;
     # the tallest tiles the LDS allows for 48 filters of 7 x 7: 128 rows for
-    # FP32 with 8 waves, 96 with 12, 110 for BF16 / FP16
+    # FP32 with 8 waves, 96 with 12, 97 for BF16 / FP16
     for nw32, ty in ((8, 8), (12, 13), (8, 64), (12, 96), (8, 128)):
         forced = tmp_path / ("forced%d_%d.txt" % (nw32, ty))
-        shape = {key: (nw32, ty) if key.startswith("p0") else (12, min(ty, 110))
+        shape = {key: (nw32, ty) if key.startswith("p0") else (12, min(ty, 97))
                  for key in keys}
         forced.write_text("".join("%d %d %s\n" % (shape[key] + (key,)) for key in keys))
         p2 = fe.Prior(k, a)
