@@ -72,10 +72,12 @@ typedef __attribute__((address_space(3))) f32x4 lquad;
 typedef __attribute__((address_space(3))) u32x2 lpair;
 
 // Waves per workgroup: FP32 is built for 8 (every operand in registers,
-// two waves per SIMD) and 12 (adjoint tables in LDS, three per SIMD);
-// BF16/FP16 for 12 (three per SIMD).
+// two waves per SIMD, u tile rows streamed during the steps) and 12
+// (adjoint tables in LDS, three per SIMD, whole u tile in the prologue);
+// 8 is the default (measured slightly faster once its rows stream), the
+// tuner may pick either.  BF16/FP16 are built for 12 (three per SIMD).
 constexpr int kWavesF32 = 8, kWavesP16 = 12;
-constexpr int kDefaultWavesF32 = 12;
+constexpr int kDefaultWavesF32 = 8;
 constexpr int kQB = 4;                // 16-pixel blocks per q-row
 constexpr int kQW = 16 * kQB;         // q-row width (pixels)
 

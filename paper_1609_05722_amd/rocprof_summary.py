@@ -15,8 +15,24 @@ plain device copy of known size in the same run.
 import argparse
 import hashlib
 import json
+import re
 import sqlite3
 import sys
+
+
+def short_name(name):
+    """A kernel name without its namespaces and trailing parameter list, so
+    that its template arguments fit a line."""
+    m = re.search(r"fused_step_kernelILi(\d)ENS0_7MathP16ILi(\d)ELi(\d)EDF16([b_])", name)
+    if m:   # mangled (the demangler leaves the 16-bit float types alone)
+        return "fused_step_kernel<%s, MathP16<%s, %s, %s> >" % (
+            m.group(1), m.group(2), m.group(3), "__bf16" if m.group(4) == "b" else "_Float16")
+    for ns in ("fe::(anonymous namespace)::", "fe::"):
+        name = name.replace(ns, "")
+    if name.startswith("void "):
+        name = name[5:]
+    cut = name.find(">(")
+    return name[:cut + 1] if cut > 0 else name
 
 
 def kernel_stats(db, like=None):
@@ -109,11 +125,11 @@ def main(argv=None):
     if a.cmd == "stats":
         for r in kernel_stats(a.db, a.kernel):
             print("%-90s calls=%-6d avg=%9.2f us min=%9.2f max=%9.2f total=%9.3f ms %5.1f%%"
-                  % (r["kernel"][:90], r["calls"], r["avg_us"], r["min_us"], r["max_us"],
-                     r["total_ms"], r["pct"]))
+                  % (short_name(r["kernel"])[:90], r["calls"], r["avg_us"], r["min_us"],
+                     r["max_us"], r["total_ms"], r["pct"]))
     elif a.cmd == "pmc":
         for k, v in pmc_means(a.db, a.kernel).items():
-            print(k[:100])
+            print(short_name(k)[:100])
             for cn, d in sorted(v.items()):
                 print("    %-34s per_dispatch=%16.1f  (instances=%d, dispatches=%d)"
                       % (cn, d["per_dispatch"], d["instances"], d["dispatches"]))

@@ -42,7 +42,7 @@ static void limits()
     // 64 filters of 7 x 7 do not fit three waves per SIMD in FP32
     CHECK(fe::max_tile_rows(bank(7, 64), FE_PREC_FP32, 12) == 0);
     CHECK(fe::max_tile_rows(bank(7, 64), FE_PREC_FP32, 8) > 0);
-    CHECK(fe::default_waves(FE_PREC_FP32) == 12 && fe::default_waves(FE_PREC_FP16) == 12);
+    CHECK(fe::default_waves(FE_PREC_FP32) == 8 && fe::default_waves(FE_PREC_FP16) == 12);
     const std::vector<int> w = fe::wave_options(FE_PREC_FP32);
     CHECK(w.size() == 2 && std::count(w.begin(), w.end(), 8) == 1 &&
           std::count(w.begin(), w.end(), 12) == 1);
