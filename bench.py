@@ -43,9 +43,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_4x512_traffic.json")
 
 
 def kernel_hash():
-    import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_1609_05722_amd.rocprof_summary import code_hash
+    return code_hash(KERNEL_SOURCE)
 
 
 def recorded_traffic(args):
@@ -57,7 +56,7 @@ def recorded_traffic(args):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha256_16") != kernel_hash() or rec.get("size") != args.size \
+    if rec.get("kernel_code_sha256_16") != kernel_hash() or rec.get("size") != args.size \
             or rec.get("iterations_checked") is None:
         return None
     return rec.get("bytes_per_launch")
@@ -378,7 +377,7 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": "fused_step_kernel<7,MathF32<7,3>> (one launch = one "
+                     "kernel": "fused_step_kernel<7,MathF32<7,3,false>> (8 waves; one launch = one "
                                "iteration of all %d jobs)" % n,
                      "launch_us": round(launch_ms * 1e3, 2),
                      "flop_per_launch": flops_per_px_it(m, nf) * px_per_launch},

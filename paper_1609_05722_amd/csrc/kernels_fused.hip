@@ -35,10 +35,10 @@
 // Reduced precision (FE_PREC_BF16 / FE_PREC_FP16): both contractions use
 // v_mfma_f32_16x16x32_{bf16,f16} (operands rounded to nearest even, FP32
 // accumulation).  K = 32 per instruction, so all m^2 taps of the forward bank
-// fit in ceil(m^2 / 32) k-steps (no VALU tap) and the adjoint takes the
-// filters 32 at a time, its tap blocks covering all m^2 taps.  The adjoint's
-// filter order is permuted so that the forward accumulators are again its
-// A operand without data movement.  The influence, the collapse, the
+// fit in ceil(m^2 / 32) k-steps (no VALU tap).  The adjoint runs in gather
+// form: psi, rounded, goes through a per-wave LDS scratch and one product
+// per block yields H directly (see MathP16), replacing the C scratch and the
+// horizontal collapse.  The influence, the H and output-row sums, the
 // inertial step and the prox stay FP32.
 #include <hip/hip_runtime.h>
 

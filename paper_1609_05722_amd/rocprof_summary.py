@@ -20,6 +20,17 @@ import sqlite3
 import sys
 
 
+def code_hash(path):
+    """First 16 hex digits of the SHA-256 of a C/HIP source with its comments
+    and whitespace removed: it changes when the code does, not when a
+    comment does."""
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
+
+
 def short_name(name):
     """A kernel name without its namespaces and trailing parameter list, so
     that its template arguments fit a line."""
@@ -86,10 +97,9 @@ def traffic(args):
     copy_write = max(dispatch_values(args.write_db, "WRITE_SIZE", args.copy_kernel))
     f_scale = args.copy_bytes / (copy_fetch * 1024.0)
     w_scale = args.copy_bytes / (copy_write * 1024.0)
-    with open(args.kernel_source, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
     rec = {
-        "kernel": args.kernel, "kernel_sha256_16": sha, "size": args.size,
+        "kernel": args.kernel, "kernel_code_sha256_16": code_hash(args.kernel_source),
+        "size": args.size,
         "fetch_kib_per_dispatch": fetch_k, "write_kib_per_dispatch": write_k,
         "dispatches": [len(fk), len(wk)],
         "copy_kernel": args.copy_kernel, "copy_bytes": args.copy_bytes,
