@@ -46,6 +46,23 @@ __device__ __forceinline__ float prox(float ut, float v, float tl, int data_term
     return a >= 0.0f ? 0.5f * (a + s) : (2.0f * tl * v) / (s - a);
 }
 
+// The same map as the fused step evaluates it: 1 / (1 + tl) precomputed
+// (q1), the hardware square root and reciprocal (about 1 ulp each) instead of
+// the correctly rounded sequences.
+__device__ __forceinline__ float prox_fast(float ut, float v, float tl, float q1, int data_term)
+{
+    if (data_term == FE_DATA_QUADRATIC_) return fmaf(tl, v, ut) * q1;
+    const float a = ut - tl;
+    const float s = __builtin_amdgcn_sqrtf(fmaf(a, a, 4.0f * tl * v));
+    return a >= 0.0f ? 0.5f * (a + s) : (2.0f * tl * v) * __builtin_amdgcn_rcpf(s - a);
+}
+
+// eq. 2.3 with the hardware square root (about 1 ulp).
+__device__ __forceinline__ float anscombe_fast(float y)
+{
+    return 2.0f * __builtin_amdgcn_sqrtf(y + 0.375f);
+}
+
 // Data-term energy per pixel without the lambda factor:
 //  quadratic 1/2 (u - v)^2; I-divergence u - v log u (+inf for u <= 0).
 __device__ __forceinline__ float data_energy(float u, float v, int data_term)

@@ -91,6 +91,7 @@ struct JobDesc {
     int iters;          // iterations this launch sequence applies
     int it0;            // iterations already applied (parity of the state)
     float tau, gamma, tl;
+    float q1;           // 1 / (1 + tl)
     int data_term;
 };
 
@@ -744,33 +745,41 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int y = y0 + orow;
         const int x = x0 + (lane < tx ? lane : tx - 1);
         // the column and, at the left or right border, its ghost columns
-        // (both when W < 2R)
+        // (both when W < 2R); side: the tile reaches a left or right border
+        // (uniform), else no lane has ghost columns and one load per a does
         const int hx = x - (x0 - R);
         const bool gl = x < R, gr = x >= W - R;
         const int hgl = gl ? (-1 - x) - (x0 - R) : hx;
         const int hgr = gr ? (2 * W - 1 - x) - (x0 - R) : hx;
+        const bool side = x0 < R || x1 > W - R;
         // sum over a of H[row - a + R][a] for one extended row; every load
-        // is issued before the first add (rows off the image weigh zero)
+        // is issued before the first add (rows off the image weigh zero).
+        // The ring slot of tile q-row row + 2R - y0 - a: one modulo for
+        // a = 0, then a decrement that wraps.
         auto row_sum = [&](int row) {
             float vh[M], vl[M], vr[M];
             bool ok[M];
+            int slot = (row + 2 * R - y0) % HR;   // the index is >= 0
 #pragma unroll
             for (int a = 0; a < M; ++a) {
                 const int qyy = row - a + R;
                 ok[a] = qyy >= 0 && qyy < H;
-                int q = ok[a] ? qyy - (y0 - R) : 0;
-                q = q >= HR ? q % HR : q;
-                const float *h = Hr + (size_t)q * M * Math::kHS + a * Math::kHS;
+                const float *h = Hr + (size_t)slot * M * Math::kHS + a * Math::kHS;
                 vh[a] = h[hx];
-                vl[a] = h[hgl];
-                vr[a] = h[hgr];
+                if (side) {
+                    vl[a] = h[hgl];
+                    vr[a] = h[hgr];
+                }
+                slot = slot == 0 ? HR - 1 : slot - 1;
             }
             float sum = 0.0f;
 #pragma unroll
             for (int a = 0; a < M; ++a) {
                 float t = vh[a];
-                t += gl ? vl[a] : 0.0f;
-                t += gr ? vr[a] : 0.0f;
+                if (side) {
+                    t += gl ? vl[a] : 0.0f;
+                    t += gr ? vr[a] : 0.0f;
+                }
                 sum += ok[a] ? t : 0.0f;
             }
             return sum;
@@ -785,7 +794,11 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         if constexpr (Math::kPairTile) uc = pf_u;
         else uc = U[(orow + 2 * R) * Math::kUS + lane + 2 * R];
         const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
-        uprev[(long)y * W + x] = prox(ut, anscombe(pf_y), J.tl, J.data_term);
+        // the column laundered: its 64-bit address is formed here each step
+        // rather than hoisted out of the step loop into a register pair
+        int xs = x;
+        asm volatile("" : "+v"(xs));
+        uprev[(long)y * W + xs] = prox_fast(ut, anscombe_fast(pf_y), J.tl, J.q1, J.data_term);
     };
 
     auto qrow = [&](int st) {
@@ -1286,6 +1299,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
                 d.tau = j.tau;
                 d.gamma = j.gamma;
                 d.tl = j.tau * j.lambda;
+                d.q1 = (float)(1.0 / (1.0 + (double)d.tl));
                 d.data_term = j.data_term == FE_DATA_AUTO
                                   ? (j.peak >= 5.0f ? FE_DATA_QUADRATIC : FE_DATA_IDIV)
                                   : j.data_term;
