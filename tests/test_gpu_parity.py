@@ -232,6 +232,25 @@ def test_mixed_precision_error_report(fe, torch, precision, peak):
     assert err.max() <= _MIXED_TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("shape", [(8, 8), (3, 3), (3, 1500), (1500, 3), (37, 53), (5, 200)])
+def test_reduced_precision_small_shapes(fe, torch, shape, precision):
+    """BF16 / FP16 operands on the shapes where every tile touches a border
+    (psi masked off the image, ghost rows and columns, partial blocks), both
+    data terms in turn, within the reduced-precision bound of the oracle."""
+    H, W = shape
+    prior, k, a = _prior(fe, 7, 48)
+    tau, gamma = step_size_for(7, 48)
+    dt = QUADRATIC if (H + W) % 2 else IDIV
+    _, y = noisy_pair(70 + H, 90 + W, H, W, 3.0)
+    print("case %dx%d %s dt=%d" % (H, W, precision, dt), flush=True)
+    ug, _ = _run(fe, torch, prior, y, 50.0, tau, gamma, 30, dt, precision=precision)
+    uo, _ = oracle.denoise(y, k, a, 50.0, tau, gamma, 30, dt)
+    err = np.abs(ug - uo)
+    print("  max|du| %.3e rms %.3e" % (err.max(), np.sqrt(np.mean(err ** 2))), flush=True)
+    assert err.max() <= _MIXED_TOL[precision]
+
+
 _ORACLE_512 = {}
 
 
