@@ -289,7 +289,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the denoiser's images are independent "
-              "and this build runs no multi-GPU path (--gpus %d requested)" % args.gpus,
+              "and the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
