@@ -1,7 +1,8 @@
 """Host-side helpers of the measurement path, on the CPU: the rocprofv3
 summary tool (kernel names, the code hash that keys the traffic record, the
 HBM traffic arithmetic on a synthetic counter database), the accuracy block
-of the benchmark line, and the benchmark's refusal of more than one GPU."""
+of the benchmark line, the benchmark's refusal of more than one GPU, and the
+build entry point's reach of both build modules."""
 import argparse
 import json
 import os
@@ -94,3 +95,13 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_build_entry_resolves_both_build_modules():
+    """build() reaches both build modules (not the oracle's re-exported
+    function) and the oracle's build runs here."""
+    import __graft_entry__ as g
+    fe_build, oracle_build = g._builders()
+    assert fe_build.__name__ == "paper_1609_05722_amd.build" and callable(fe_build.build)
+    assert oracle_build.__name__ == "oracle.build" and callable(oracle_build.build)
+    assert os.path.exists(oracle_build.build())
