@@ -119,11 +119,32 @@ static void keys()
     CHECK(fe::batch_key(FE_PREC_FP32, z, 2) == "p0:10x20,10x20,");
 }
 
+// The largest jobs: tile counts in 64-bit arithmetic, beyond one launch's
+// 2^21 workgroups for a 3-row image of 2^31 - 2 pixels (the step then splits
+// its launches over tile ranges), and a batch of them beyond 2^31 tiles.
+static void huge()
+{
+    const fe::FusedBank b7 = bank(7, 48);
+    fe_job thin{};
+    thin.height = 3;
+    thin.width = 715827882;
+    thin.precision = FE_PREC_FP32;
+    fe::AdvanceItem one[1] = {{&thin, nullptr, 0, 4}};
+    fe::Plan p;
+    fe::make_plan(b7, FE_PREC_FP32, one, 1, &p, 8);
+    CHECK(p.jobs_ntx[0] == (715827882 + 57) / 58 && p.jobs_nty[0] == 1);
+    CHECK(p.ntiles == 12341861L && p.ntiles > (1L << 21));
+    std::vector<fe::AdvanceItem> many(200, fe::AdvanceItem{&thin, nullptr, 0, 4});
+    fe::make_plan(b7, FE_PREC_FP32, many.data(), 200, &p, 8);
+    CHECK(p.ntiles == 200L * 12341861L && p.ntiles > 2147483647L);
+}
+
 int main()
 {
     limits();
     random_batches();
     keys();
+    huge();
     std::printf("OK\n");
     return 0;
 }
