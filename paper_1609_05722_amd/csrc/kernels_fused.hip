@@ -379,7 +379,7 @@ struct MathF32 {
 // Tables (8 values of P per lane per slot):
 //   t0 forward A   [KS][NFB][64][8]  A[filter 16fb + l%16][tap 32s + 8(l/16) + e]
 //   t1 adjoint B   [KG][64][8]       B[slot 4s + l/16 = (b, j), filter 8j + e][a = l%16]
-//                                    = 2 alpha_f k_f(a, b), slot = b * NJ + j
+//                                    = 2 alpha_f k_f(a, b), slot = j * M + b
 template <int M, int NFB, typename P>
 struct MathP16 {
     using G = Geo<M>;
@@ -462,13 +462,17 @@ struct MathP16 {
                 }
             }
         }
-        // slot 4s + g = (b, j): psi of filters 8j.. at q-position p - b + R
-        // (row p - b + 2R); padding slots (zero B) read row p + R
+        // slot 4s + g = (b, j) = (slot % M, slot / M): psi of filters 8j..
+        // at q-position p - b + R (row p - b + 2R); padding slots (zero B)
+        // read row p + R.  The four lane groups of a k-step read mostly the
+        // same filter group at different shifts (different rows): with the
+        // groups reading one row at different filter groups instead, the
+        // reads had 3x the bank-conflict cycles (measured).
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
             const int sg = 4 * s + g;
             const bool ok = sg < NJ * M;
-            const int b = ok ? sg / NJ : G::R, j = ok ? sg % NJ : 0;
+            const int b = ok ? sg % M : G::R, j = ok ? sg / M : 0;
             aoff[s] = (p - b + 2 * G::R) * PS + 8 * j;
         }
     }
@@ -1056,9 +1060,9 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
     for (int s = 0; s < KG; ++s)
         for (int l = 0; l < 64; ++l)
             for (int e = 0; e < 8; ++e) {
-                // B[slot (b, j), filter 8j + e][a]: slot 4s + l/16 = b * NJ + j
+                // B[slot (b, j), filter 8j + e][a]: slot 4s + l/16 = j * m + b
                 const int sg = 4 * s + (l >> 4), a = l & 15;
-                const int b = sg / NJ, f = 8 * (sg % NJ) + e;
+                const int b = sg % m, f = 8 * (sg / m) + e;
                 pa[((size_t)s * 64 + l) * 8 + e] =
                     (sg < NJ * m && a < m) ? a2(f) * tap(f, a * m + b) : 0.0f;
             }
