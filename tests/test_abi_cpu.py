@@ -132,3 +132,16 @@ def test_binding_rejects_host_or_malformed_tensors():
                 torch.zeros(8, 16)[:, ::2]):
         with pytest.raises(ValueError):
             fe.make_jobs([fe.JobSpec(bad, 1.0, 1, 0.1, 0.5)])
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libfe.so every entry point raises: there is no other path."""
+    import paper_1609_05722_amd as fe
+    monkeypatch.setattr(fe, "_lib", None)
+    monkeypatch.setattr(fe, "LIB_PATH", str(tmp_path / "libfe.so"))
+    with pytest.raises(ImportError, match="not built"):
+        fe.library()
+    k = np.zeros((8, 3, 3), np.float32)
+    k[:, 1, 1] = 1.0
+    with pytest.raises(ImportError, match="not built"):
+        fe.Prior(k, np.ones(8, np.float32))
