@@ -258,6 +258,118 @@ def batch_report(fe, torch, prior, args, tau, gamma, log=None):
     return res
 
 
+def energy_report(fe, torch, prior, cfg, counts, stream, reps=10):
+    """fe_energy_grad (the energy and its gradient, off the per-iteration
+    path) on the four images of the workload at u = v (the Anscombe-domain
+    start): gradient only (asynchronous, HIP events) and energy + gradient
+    (the energy returns to the host, so each call synchronises; wall clock).
+    Work per pixel: both filter banks, 2 * 2 * N_f * m^2 flops, and the psi
+    planes written and read back through HBM (2 * 4 * N_f bytes) plus u, y
+    and the gradient (12 bytes)."""
+    import ctypes
+    lib = fe.library()
+    m, nf = cfg["m"], cfg["n_filters"]
+    H, W = counts[0].shape
+    px = H * W
+    us = [2.0 * torch.sqrt(c + 0.375) for c in counts]
+    grads = [torch.empty_like(u) for u in us]
+    sz = ctypes.c_size_t()
+    st = lib.fe_energy_grad_workspace_size(prior.handle, H, W, ctypes.byref(sz))
+    if st != 0:
+        raise fe.FeError(st, lib.fe_last_error().decode())
+    ws = fe.alloc_workspace(sz.value, "cuda")
+    flop_px = flops_per_px_it(m, nf)
+    bytes_px = 2 * 4 * nf + 12
+    out = {"workload": "%d images of %dx%d, %d %dx%d filters, u = v" % (len(counts), H, W,
+                                                                        nf, m, m),
+           "flop_per_px": flop_px, "hbm_bytes_per_px": bytes_px}
+    for prec in ("fp32", "bf16"):
+        pr = fe._PREC[prec]
+        e = ctypes.c_double()
+
+        def call(i, want_energy):
+            j = cfg["jobs"][i]
+            r = lib.fe_energy_grad(prior.handle, H, W, fe._ptr(counts[i]), fe._ptr(us[i]),
+                                   float(j.lam), int(j.data_term), pr,
+                                   ctypes.byref(e) if want_energy else None,
+                                   fe._ptr(grads[i]), fe._ptr(ws), ws.numel(),
+                                   fe._stream_handle(stream))
+            if r != 0:
+                raise fe.FeError(r, lib.fe_last_error().decode())
+
+        for i in range(len(counts)):
+            call(i, True)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            for i in range(len(counts)):
+                call(i, False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_grad = ev0.elapsed_time(ev1) / (reps * len(counts))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for i in range(len(counts)):
+                call(i, True)
+        ms_both = (time.perf_counter() - t0) * 1e3 / (reps * len(counts))
+        out[prec] = {"grad_ms_per_image": round(ms_grad, 4),
+                     "energy_grad_ms_per_image": round(ms_both, 4),
+                     "grad_Mpixel_per_s": round(px / (ms_grad * 1e-3) / 1e6, 1),
+                     "achieved_TFLOPs": round(flop_px * px / (ms_grad * 1e-3) / 1e12, 3),
+                     "frac_of_fp32_vector_peak": round(flop_px * px / (ms_grad * 1e-3) / 1e12
+                                                       / FP32_PEAK_TFLOPS, 4),
+                     "hbm_algorithmic_GBs": round(bytes_px * px / (ms_grad * 1e-3) / 1e9, 1)}
+    del ws, us, grads
+    return out
+
+
+def binned_report(fe, torch, prior, cfg, counts, stream, tau, gamma, reps=3):
+    """fe_denoise_binned (3 x 3 binning, the denoiser on the binned counts with
+    the data term of 9x the peak, bilinear upsampling) on the four images of
+    the workload, one call over all four, HIP events around each call."""
+    import ctypes
+    from synth.workloads import lambda_for_peak
+    lib = fe.library()
+    specs = [fe.JobSpec(c, lambda_for_peak(9 * j.peak), j.iterations, tau, gamma,
+                        data_term="auto", peak=j.peak)
+             for c, j in zip(counts, cfg["jobs"])]
+    arr, keep = fe.make_jobs(specs)
+    n = len(specs)
+    sz = ctypes.c_size_t()
+    st = lib.fe_binned_workspace_size(prior.handle, arr, n, ctypes.byref(sz))
+    if st != 0:
+        raise fe.FeError(st, lib.fe_last_error().decode())
+    ws = fe.alloc_workspace(sz.value, "cuda")
+
+    def call():
+        r = lib.fe_denoise_binned(prior.handle, arr, n, fe._ptr(ws), ws.numel(),
+                                  fe._stream_handle(stream))
+        if r != 0:
+            raise fe.FeError(r, lib.fe_last_error().decode())
+
+    call()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        call()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    H, W = counts[0].shape
+    hb, wb = (H + 2) // 3, (W + 2) // 3
+    its = cfg["jobs"][0].iterations
+    del ws, keep
+    return {"workload": "%d images of %dx%d binned to %dx%d, %d iterations, one call" % (
+                n, H, W, hb, wb, its),
+            "ms_per_call": round(ms, 4), "images_per_s": round(n / (ms * 1e-3), 1),
+            "binned_Mpixel_iter_per_s": round(n * hb * wb * its / (ms * 1e-3) / 1e6, 1),
+            "full_res_Mpixel_per_s": round(n * H * W / (ms * 1e-3) / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +395,10 @@ def main():
                          "is python -m paper_1609_05722_amd.serving)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the bf16 / fp16 contraction timings")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="skip the energy / gradient timing (fe_energy_grad)")
+    ap.add_argument("--no-binned", action="store_true",
+                    help="skip the binning-variant timing (fe_denoise_binned)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a "
                          "known-size reference for HBM byte counters)")
@@ -430,6 +546,11 @@ def main():
 
     if not args.no_mixed:
         section("mixed_precision", mixed_section)
+    if not args.no_energy:
+        section("energy_grad", lambda: energy_report(fe, torch, prior, cfg, counts, stream))
+    if not args.no_binned:
+        section("binned", lambda: binned_report(fe, torch, prior, cfg, counts, stream,
+                                                tau, gamma))
     if not args.no_batch:
         section("batch", lambda: batch_report(fe, torch, prior, args, tau, gamma,
                                               log=lambda t: print(t, file=sys.stderr,

@@ -13,26 +13,18 @@ namespace fe {
 constexpr int kMaxM = 7;         // largest filter side built
 constexpr int kMaxFilters = 64;  // largest filter count built
 
-// Per-job iteration parameters as the kernels consume them.
-struct StepParams {
-    float tau;        // iPiano step
-    float gamma;      // iPiano inertia
-    float tau_lambda; // tau * lambda, the prox weight
-    int data_term;    // FE_DATA_QUADRATIC or FE_DATA_IDIV
-};
-
 // Filter bank on the device, in the layouts the kernels read.
 struct DeviceBank {
     int m = 0, nf = 0;
     float *taps = nullptr;     // [nf][m*m] correlation taps
+    float *taps_r[2] = {};     // the same rounded to BF16, FP16 (held as float)
     float *alpha2 = nullptr;   // [nf] 2 * alpha_i (the influence's factor)
     float *alpha = nullptr;    // [nf] alpha_i
-    // MFMA operand tables, one float per lane per register slot (see the
-    // fused step kernel for the exact lane layout).
-    float *mfma_fwd = nullptr; // forward  A operands
-    float *mfma_adj = nullptr; // adjoint  B operands
-    float *mfma_last = nullptr;// the tap left over after groups of four
-    int nfb = 0;               // filter blocks of 16 (zero-padded)
+    // the taps as the contractions of a precision (FE_PREC_*) use them
+    const float *taps_for(int precision) const
+    {
+        return precision == 1 ? taps_r[0] : precision == 2 ? taps_r[1] : taps;
+    }
 };
 
 // ---- elementwise kernels (kernels_pointwise.hip) --------------------------
@@ -65,13 +57,6 @@ hipError_t launch_direct_forward(const DeviceBank &bank, const float *u,
                                  const float *counts, float lambda,
                                  int data_term, int precision, int *n_blocks,
                                  hipStream_t s);
-// u_next = prox(u - tau * sum_i K_i^T psi_i + gamma (u - u_prev)); u_next may
-// alias u_prev (each pixel is read before it is written by one thread).
-hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
-                                      const float *u, const float *u_prev,
-                                      const float *counts, float *u_next,
-                                      int H, int W, StepParams p,
-                                      hipStream_t s);
 // grad = sum_i K_i^T psi_i + grad D(u, v); precision rounds the operands
 // of K_i^T psi_i (FP32 accumulation).
 hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,

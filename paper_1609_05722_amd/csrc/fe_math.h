@@ -11,19 +11,6 @@ namespace fe {
 // eq. 2.3
 __device__ __forceinline__ float anscombe(float y) { return 2.0f * sqrtf(y + 0.375f); }
 
-// alpha_i rho'(z) with rho(z) = log(1 + z^2) (eq. 2.6): 2 alpha_i z / (1 + z^2);
-// `alpha2` holds 2 alpha_i.
-__device__ __forceinline__ float influence(float z, float alpha2)
-{
-    return alpha2 * z / fmaf(z, z, 1.0f);
-}
-
-// Same with the hardware reciprocal (about 1 ulp) instead of a division.
-__device__ __forceinline__ float influence_fast(float z, float alpha2)
-{
-    return alpha2 * z * __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f));
-}
-
 // Explicit part of the iPiano step (eq. 2.8): u - tau g + gamma (u - u_prev).
 __device__ __forceinline__ float inertial_step(float u, float u_prev, float g,
                                                float tau, float gamma)
@@ -31,23 +18,13 @@ __device__ __forceinline__ float inertial_step(float u, float u_prev, float g,
     return fmaf(-tau, g, u) + gamma * (u - u_prev);
 }
 
-// Proximal map of tau G (eq. 2.9).  tl = tau * lambda.
+// Proximal map of tau G (eq. 2.9).  tl = tau * lambda, q1 = 1 / (1 + tl).
 //  quadratic (eq. 3.5):   (u~ + tl v) / (1 + tl)
 //  I-divergence (eq. 3.3 with y -> v, eq. 3.6):
 //     (a + sqrt(a^2 + 4 tl v)) / 2,  a = u~ - tl;
 //  for a < 0 the algebraically equal 2 tl v / (sqrt(a^2 + 4 tl v) - a)
 //  avoids the cancellation of a + sqrt(...).
-__device__ __forceinline__ float prox(float ut, float v, float tl, int data_term)
-{
-    if (data_term == FE_DATA_QUADRATIC_) return (ut + tl * v) / (1.0f + tl);
-    const float a = ut - tl;
-    const float c = 4.0f * tl * v;
-    const float s = sqrtf(fmaf(a, a, c));
-    return a >= 0.0f ? 0.5f * (a + s) : (2.0f * tl * v) / (s - a);
-}
-
-// The same map as the fused step evaluates it: 1 / (1 + tl) precomputed
-// (q1), the hardware square root and reciprocal (about 1 ulp each) instead of
+// The hardware square root and reciprocal (about 1 ulp each) stand in for
 // the correctly rounded sequences.
 __device__ __forceinline__ float prox_fast(float ut, float v, float tl, float q1, int data_term)
 {

@@ -283,7 +283,23 @@ fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out)
     fe::DeviceBank &b = c->bank;
     b.m = m;
     b.nf = nf;
-    hipError_t e = hipMalloc((void **)&b.taps, sizeof(float) * nf * m * m);
+    // the taps rounded once to BF16 and FP16 (nearest even), for the direct
+    // kernels' reduced-precision contractions
+    const size_t nt = (size_t)nf * m * m;
+    std::vector<float> tr[2] = {std::vector<float>(nt), std::vector<float>(nt)};
+    for (size_t i = 0; i < nt; ++i) {
+        uint32_t w;
+        std::memcpy(&w, &c->taps[i], 4);
+        w = (w + 0x7FFFu + ((w >> 16) & 1u)) & 0xFFFF0000u;
+        std::memcpy(&tr[0][i], &w, 4);
+        tr[1][i] = (float)(_Float16)c->taps[i];
+    }
+    hipError_t e = hipMalloc((void **)&b.taps, sizeof(float) * nt);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+        e = hipMalloc((void **)&b.taps_r[r], sizeof(float) * nt);
+        if (e == hipSuccess)
+            e = hipMemcpy(b.taps_r[r], tr[r].data(), sizeof(float) * nt, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&b.alpha2, sizeof(float) * nf);
     if (e == hipSuccess) e = hipMalloc((void **)&b.alpha, sizeof(float) * nf);
     if (e == hipSuccess)
@@ -308,6 +324,8 @@ void fe_destroy(fe_ctx *c)
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipFree(c->bank.taps);
+    (void)hipFree(c->bank.taps_r[0]);
+    (void)hipFree(c->bank.taps_r[1]);
     (void)hipFree(c->bank.alpha2);
     (void)hipFree(c->bank.alpha);
     fe::fused_release(&c->fused);

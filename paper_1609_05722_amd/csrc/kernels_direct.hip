@@ -1,11 +1,10 @@
-// Direct filter-bank kernels: one thread per pixel, no matrix cores.
+// Direct filter-bank kernels of the energy and gradient entry point: one
+// thread per pixel, no matrix cores.
 //
-// These compute the prior's gradient of eq. 3.2 in two passes through HBM:
-// the forward pass writes psi_i = alpha_i rho'(K_i u) for every filter, the
-// adjoint pass gathers sum_i K_i^T psi_i per pixel.  They serve the energy
-// and gradient entry point (which also needs the Student-t energy of
-// eq. 2.5/2.6) and any filter shape the fused matrix-core step is not built
-// for.
+// The prior's gradient (eq. 3.2) takes two passes through HBM: the forward
+// pass writes psi_i = alpha_i rho'(K_i u) for every filter (and the
+// Student-t energy of eq. 2.5/2.6 when asked), the adjoint pass gathers
+// sum_i K_i^T psi_i per pixel from LDS tiles of psi.
 #include "fe_internal.h"
 #include "fe_math.h"
 
@@ -78,11 +77,11 @@ void forward_kernel(const float *__restrict__ taps,
     const long plane = (long)H * W;
     for (int i = 0; i < nf; ++i) {
         if (!in) break;
-        const float *k = taps + i * M * M;
+        const float *k = taps + i * M * M;   // already rounded to the precision
         float z = 0.0f;
 #pragma unroll
-        for (int t = 0; t < M * M; ++t) z = fmaf(operand<PREC>(k[t]), e[t], z);
-        psi[i * plane + (long)y * W + x] = influence(z, alpha2[i]);
+        for (int t = 0; t < M * M; ++t) z = fmaf(k[t], e[t], z);
+        psi[i * plane + (long)y * W + x] = alpha2[i] * z * __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f));
         if (rho_partial) rho_acc += alpha[i] * log1pf(z * z);
     }
     if (rho_partial) {
@@ -101,72 +100,26 @@ void forward_kernel(const float *__restrict__ taps,
     }
 }
 
-// sum_i K_i^T psi_i at pixel (y, x): the transpose of "extend, then
-// correlate".  The extended position s = (sy, sx) receives
+// grad E at pixel (y, x): the transpose of "extend, then correlate" plus the
+// data term.  The extended position s = (sy, sx) receives
 //   G(s) = sum_i sum_{a,b} k_i[a][b] psi_i(sy - a + R, sx - b + R)
 // (psi = 0 outside the image), and every extended position mirroring
-// (y, x) adds onto it: the pixel itself, plus the ghost row -1-y (y < R) or
-// 2H-1-y (y >= H-R), likewise for columns.
-template <int M, int PREC>
-__device__ float adjoint_at(const float *__restrict__ taps, int nf,
-                            const float *__restrict__ psi, int H, int W,
-                            int y, int x)
-{
-    constexpr int R = (M - 1) / 2;
-    int rows[3], cols[3];
-    int nr = 0, nc = 0;
-    if (y < R) rows[nr++] = -1 - y;
-    rows[nr++] = y;
-    if (y >= H - R) rows[nr++] = 2 * H - 1 - y;
-    if (x < R) cols[nc++] = -1 - x;
-    cols[nc++] = x;
-    if (x >= W - R) cols[nc++] = 2 * W - 1 - x;
-    const long plane = (long)H * W;
-    float g = 0.0f;
-    for (int ir = 0; ir < nr; ++ir) {
-        for (int ic = 0; ic < nc; ++ic) {
-            const int sy = rows[ir], sx = cols[ic];
-            float acc = 0.0f;
-            for (int i = 0; i < nf; ++i) {
-                const float *k = taps + i * M * M;
-                const float *p = psi + i * plane;
-#pragma unroll
-                for (int a = 0; a < M; ++a) {
-                    const int qy = sy - a + R;
-                    if (qy < 0 || qy >= H) continue;
-#pragma unroll
-                    for (int b = 0; b < M; ++b) {
-                        const int qx = sx - b + R;
-                        if (qx < 0 || qx >= W) continue;
-                        acc = fmaf(operand<PREC>(k[a * M + b]),
-                                   operand<PREC>(p[(long)qy * W + qx]), acc);
-                    }
-                }
-            }
-            g += acc;
-        }
-    }
-    return g;
-}
-
-template <int M>
-__global__ __launch_bounds__(kBX * kBY)
-void adjoint_step_kernel(const float *__restrict__ taps, int nf,
-                         const float *__restrict__ psi,
-                         const float *__restrict__ u,
-                         const float *u_prev, const float *__restrict__ counts,
-                         float *u_next, int H, int W, StepParams prm)
-{
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    const long p = (long)y * W + x;
-    const float g = adjoint_at<M, 0>(taps, nf, psi, H, W, y, x);
-    const float uc = u[p];
-    const float ut = inertial_step(uc, u_prev[p], g, prm.tau, prm.gamma);
-    u_next[p] = prox(ut, anscombe(counts[p]), prm.tau_lambda, prm.data_term);
-}
-
+// (y, x) adds onto it: the pixel itself, plus the ghost row -1-y (y < R) and
+// the ghost row 2H-1-y (y >= H-R), likewise for columns.
+//
+// Per filter, the workgroup stages psi_i on rows y0 - 2R .. y0 + kBY + 3R - 1
+// (and the same columns) in LDS, zero off the image, so the tap loop reads
+// LDS only and needs no bounds tests.  That window holds every q a pixel of
+// the block reaches: a mirrored row s lies in [y0 - R, y0 + kBY + 2R)
+// (s = -1-y only occurs with y0 = 0; s = 2H-1-y <= H+R-1, and a block holding
+// a row y >= H-R has H < y0 + kBY + R), and q = s - a + R with 0 <= a < m.
+// The tile's rows are TS floats apart, 16 mod 32, so that the four 16-lane
+// rows of a wave read disjoint banks (a stride of kBX + 5R itself, -1 mod 32
+// for 7 x 7, put them on nearly the same banks).  Tiles alternate between two
+// LDS buffers and the next filter's tile is loaded into registers while the
+// current one is summed: one barrier per filter (a thread storing tile i + 1
+// has passed the barrier of tile i, which every thread reached after summing
+// tile i - 1, the buffer it overwrites).
 template <int M, int PREC>
 __global__ __launch_bounds__(kBX * kBY)
 void adjoint_grad_kernel(const float *__restrict__ taps, int nf,
@@ -176,12 +129,68 @@ void adjoint_grad_kernel(const float *__restrict__ taps, int nf,
                          float *__restrict__ grad, int H, int W, float lambda,
                          int data_term)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    if (x >= W || y >= H) return;
-    const long p = (long)y * W + x;
-    const float g = adjoint_at<M, PREC>(taps, nf, psi, H, W, y, x);
-    grad[p] = g + lambda * data_gradient(u[p], anscombe(counts[p]), data_term);
+    constexpr int R = (M - 1) / 2;
+    constexpr int TH = kBY + 5 * R, TW = kBX + 5 * R, TN = TH * TW;
+    constexpr int TS = (TW + 16 + 31) / 32 * 32 - 16;   // >= TW, 16 mod 32
+    constexpr int NT = kBX * kBY;
+    constexpr int LPT = (TN + NT - 1) / NT;   // tile elements per thread
+    __shared__ float tile[2][TH * TS];
+    const int y0 = blockIdx.y * kBY, x0 = blockIdx.x * kBX;
+    const int y = y0 + threadIdx.y, x = x0 + threadIdx.x;
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    const bool in = (x < W) && (y < H);
+    // this thread's tile elements: LDS slot, and plane offset or -1 off the
+    // image (slot -1: beyond the tile)
+    int goff[LPT], slot[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+        const int t = tid + j * NT;
+        const int ty = t / TW, tx = t % TW;
+        const int qy = y0 - 2 * R + ty, qx = x0 - 2 * R + tx;
+        slot[j] = t < TN ? ty * TS + tx : -1;
+        goff[j] = (t < TN && qy >= 0 && qy < H && qx >= 0 && qx < W) ? qy * W + qx : -1;
+    }
+    // mirrored extended positions: slot 0 the pixel, 1 the low ghost, 2 the high
+    const int sy[3] = {y, -1 - y, 2 * H - 1 - y}, sx[3] = {x, -1 - x, 2 * W - 1 - x};
+    const bool vy[3] = {in, in && y < R, in && y >= H - R};
+    const bool vx[3] = {true, x < R, x >= W - R};
+    const long plane = (long)H * W;
+    float pf[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) pf[j] = goff[j] >= 0 ? operand<PREC>(psi[goff[j]]) : 0.0f;
+    float g = 0.0f;
+    for (int i = 0; i < nf; ++i) {
+        float *tb = tile[i & 1];
+#pragma unroll
+        for (int j = 0; j < LPT; ++j)
+            if (slot[j] >= 0) tb[slot[j]] = pf[j];
+        __syncthreads();
+        if (i + 1 < nf) {
+            const float *p = psi + (i + 1) * plane;
+#pragma unroll
+            for (int j = 0; j < LPT; ++j)
+                pf[j] = goff[j] >= 0 ? operand<PREC>(p[goff[j]]) : 0.0f;
+        }
+        const float *k = taps + i * M * M;   // already rounded to the precision
+#pragma unroll
+        for (int ir = 0; ir < 3; ++ir) {
+#pragma unroll
+            for (int ic = 0; ic < 3; ++ic) {
+                if (!(vy[ir] && vx[ic])) continue;
+                // tile element of q = (s - a + R, s - b + R) at a = b = 0
+                const float *tp = tb + (sy[ir] - y0 + 3 * R) * TS + (sx[ic] - x0 + 3 * R);
+                float acc = 0.0f;
+#pragma unroll
+                for (int a = 0; a < M; ++a)
+#pragma unroll
+                    for (int b = 0; b < M; ++b) acc = fmaf(k[a * M + b], tp[-a * TS - b], acc);
+                g += acc;
+            }
+        }
+    }
+    if (!in) return;
+    const long q = (long)y * W + x;
+    grad[q] = g + lambda * data_gradient(u[q], anscombe(counts[q]), data_term);
 }
 
 dim3 grid2d(int H, int W) { return dim3((W + kBX - 1) / kBX, (H + kBY - 1) / kBY); }
@@ -193,13 +202,6 @@ int direct_forward_blocks(int H, int W)
     const dim3 g = grid2d(H, W);
     return (int)(g.x * g.y);
 }
-
-#define FE_DISPATCH_M(m, CALL) \
-    switch (m) {               \
-    case 3: CALL(3); break;    \
-    case 5: CALL(5); break;    \
-    case 7: CALL(7); break;    \
-    default: return hipErrorInvalidValue; }
 
 #define FE_DISPATCH_MP(m, prec, CALL)                                        \
     switch ((m) * 10 + (prec)) {                                             \
@@ -224,25 +226,11 @@ hipError_t launch_direct_forward(const DeviceBank &bank, const float *u,
     const dim3 g = grid2d(H, W), b(kBX, kBY);
     if (n_blocks) *n_blocks = (int)(g.x * g.y);
 #define FE_CALL(MM, PP)                                                      \
-    forward_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps, bank.alpha2, bank.alpha, \
+    forward_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps_for(PP), bank.alpha2,      \
+                                           bank.alpha,                         \
                                            bank.nf, u, H, W, psi, rho_partial, \
                                            data_partial, counts, lambda, data_term)
     FE_DISPATCH_MP(bank.m, precision, FE_CALL)
-#undef FE_CALL
-    return hipGetLastError();
-}
-
-hipError_t launch_direct_adjoint_step(const DeviceBank &bank, const float *psi,
-                                      const float *u, const float *u_prev,
-                                      const float *counts, float *u_next,
-                                      int H, int W, StepParams p,
-                                      hipStream_t s)
-{
-    const dim3 g = grid2d(H, W), b(kBX, kBY);
-#define FE_CALL(MM)                                                          \
-    adjoint_step_kernel<MM><<<g, b, 0, s>>>(bank.taps, bank.nf, psi, u,       \
-                                            u_prev, counts, u_next, H, W, p)
-    FE_DISPATCH_M(bank.m, FE_CALL)
 #undef FE_CALL
     return hipGetLastError();
 }
@@ -254,7 +242,8 @@ hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,
 {
     const dim3 g = grid2d(H, W), b(kBX, kBY);
 #define FE_CALL(MM, PP)                                                      \
-    adjoint_grad_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps, bank.nf, psi, u,   \
+    adjoint_grad_kernel<MM, PP><<<g, b, 0, s>>>(bank.taps_for(PP), bank.nf,   \
+                                                psi, u,                       \
                                                 counts, grad, H, W, lambda,   \
                                                 data_term)
     FE_DISPATCH_MP(bank.m, precision, FE_CALL)

@@ -162,6 +162,31 @@ def test_energy_and_gradient(fe, torch, data_term):
         np.max(np.abs(g - go))
 
 
+@pytest.mark.parametrize("m,nf", [(3, 8), (5, 24), (7, 48)])
+@pytest.mark.parametrize("shape", [(18, 17), (33, 50), (16, 16), (7, 41), (3, 20), (50, 3),
+                                   (97, 130)])
+def test_gradient_shapes(fe, torch, m, nf, shape):
+    """The gradient's LDS-tiled adjoint at the borders: images whose last
+    16-row or 16-column block ends within r of the edge (H or W = 1, 2 mod
+    16), one block exactly, sizes down to r, and several blocks; against the
+    oracle's gradient."""
+    H, W = shape
+    if min(H, W) < (m - 1) // 2:
+        pytest.skip("below the filter radius")
+    prior, k, a = _prior(fe, m, nf)
+    x, y = noisy_pair(31 + H, 32 + W, H, W, 2.0)
+    v = oracle.anscombe(y)
+    u32 = (v + np.random.default_rng(H * W).uniform(-0.3, 0.3, v.shape)).astype(np.float32)
+    e, g = fe.energy_grad(torch.from_numpy(y).cuda(), torch.from_numpy(u32).cuda(),
+                          prior, 30.0, IDIV)
+    eo, go = oracle.energy_grad(u32.astype(np.float64), v, k.astype(np.float64),
+                                a.astype(np.float64), np.float32(30.0), IDIV)
+    assert abs(e - eo) <= 1e-5 * abs(eo), (e, eo)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(g - go)) <= 1e-4 * max(np.max(np.abs(go)), 1e-3), \
+        np.max(np.abs(g - go))
+
+
 def test_stepping_matches_denoise_and_resumes(fe, torch):
     """fe_begin + fe_advance in pieces + fe_end is bitwise fe_denoise; a
     state copied out after some iterations and restored continues to the
