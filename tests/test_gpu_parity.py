@@ -106,21 +106,37 @@ def test_zero_weights_keep_v(fe, torch, data_term):
     assert _rel_err(ug, oracle.anscombe(y)) <= 1e-5
 
 
-def test_full_size_peak4_idiv(fe, torch):
-    """512 x 512 at peak 4 (I-div branch), 48 filters of 7 x 7, 200 its."""
-    cfg = fp32_config()
-    j = [jj for jj in cfg["jobs"] if jj.peak == 4.0][0]
-    tau, gamma = step_size_for(7, 48)
-    _, y = j.arrays()
-    _check(fe, torch, 7, 48, y, j.lam, tau, gamma, j.iterations, j.data_term)
+_ORACLE_512 = {}
 
 
-def test_full_size_peak8_quadratic(fe, torch):
+def _oracle_512(j, k, a, tau, gamma):
+    """The oracle's result on one 512 x 512 baseline image, computed once per
+    peak and shared by the FP32 and the reduced-precision tests."""
+    if j.peak not in _ORACLE_512:
+        _, y = j.arrays()
+        _ORACLE_512[j.peak] = oracle.denoise(y, k, a, j.lam, tau, gamma, j.iterations,
+                                             j.data_term)
+    return _ORACLE_512[j.peak]
+
+
+@pytest.mark.parametrize("peak", [1.0, 2.0, 4.0, 8.0])
+def test_full_size_fp32(fe, torch, peak):
+    """The four 512 x 512 baseline images (peaks 1, 2, 4: I-div; 8:
+    quadratic), 48 filters of 7 x 7, 200 iterations, every pixel of u_hat
+    and x_hat against the oracle.  Peaks 1 and 2 take the prox's a < 0
+    branch (eq. 3.3 in its cancellation-free form) and the I_C clamp most
+    often."""
     cfg = fp32_config()
-    j = [jj for jj in cfg["jobs"] if jj.peak == 8.0][0]
+    j = [jj for jj in cfg["jobs"] if jj.peak == peak][0]
+    prior, k, a = _prior(fe, 7, 48)
     tau, gamma = step_size_for(7, 48)
     _, y = j.arrays()
-    _check(fe, torch, 7, 48, y, j.lam, tau, gamma, j.iterations, j.data_term)
+    print("case 512x512 fp32 peak %g dt=%d" % (peak, j.data_term), flush=True)
+    ug, xg = _run(fe, torch, prior, y, j.lam, tau, gamma, j.iterations, j.data_term)
+    uo, xo = _oracle_512(j, k, a, tau, gamma)
+    eu, ex = _rel_err(ug, uo), _rel_err(xg, xo)
+    print("  max rel err u %.2e x %.2e" % (eu, ex), flush=True)
+    assert eu <= TOL and ex <= TOL, (eu, ex)
 
 
 def test_batch_equals_alone_and_is_deterministic(fe, torch):
@@ -276,9 +292,6 @@ def test_reduced_precision_small_shapes(fe, torch, shape, precision):
     assert err.max() <= _MIXED_TOL[precision]
 
 
-_ORACLE_512 = {}
-
-
 @pytest.mark.parametrize("peak", [1.0, 2.0, 4.0, 8.0])
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_mixed_precision_full_size(fe, torch, precision, peak):
@@ -292,10 +305,7 @@ def test_mixed_precision_full_size(fe, torch, precision, peak):
     x, y = j.arrays()
     ug, xg = _run(fe, torch, prior, y, j.lam, tau, gamma, j.iterations, j.data_term,
                   precision=precision)
-    if peak not in _ORACLE_512:
-        _ORACLE_512[peak] = oracle.denoise(y, k, a, j.lam, tau, gamma, j.iterations,
-                                           j.data_term)
-    uo, xo = _ORACLE_512[peak]
+    uo, xo = _oracle_512(j, k, a, tau, gamma)
     err = np.abs(ug - uo)
     dpsnr = _psnr(xg, x, j.peak) - _psnr(xo, x, j.peak)
     print("precision %s 512x512 peak %g: max|du| %.3e rms %.3e dPSNR %+.4f dB"
