@@ -146,6 +146,24 @@ fe_status fe_advance(const fe_ctx *ctx, const fe_job *jobs, float *const *states
                      const int32_t *done, const int32_t *count, int32_t n,
                      void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ---- allocation-free stepping --------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fe_advance with the job table of its launches in a static device array
+ * owned by the library (256 KiB on every device the library runs on, held
+ * until the process ends) instead of a caller workspace.  Same arguments,
+ * checks and results as fe_advance (bitwise); the caller still owns the
+ * jobs' counts and states.  Allocates no device memory.
+ * At most FE_NOALLOC_MAX_JOBS jobs per call, else FE_ERR_INVALID.  The
+ * array is shared by every call on a device and keeps the last call's
+ * table: calls on one stream are ordered, but calls that overlap on one
+ * device (other streams, threads or contexts) race on it, and the caller
+ * must serialise them.  Async. */
+#define FE_NOALLOC_MAX_JOBS 2048
+fe_status fe_advance_noalloc(const fe_ctx *ctx, const fe_job *jobs, float *const *states,
+                             const int32_t *done, const int32_t *count, int32_t n,
+                             void *hip_stream);
+
 /* x_hat = I_C(u^done) (eq. 2.4) into job.out, and u^done into
  * job.out_anscombe, for every job (either output may be NULL).  Async. */
 fe_status fe_end(const fe_ctx *ctx, const fe_job *jobs, float *const *states,

@@ -32,7 +32,7 @@ EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
            "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_load",
            "fe_server_destroy", "fe_server_last_error", "fe_autotune", "fe_tuning_save",
            "fe_tuning_load", "fe_advance_graph_create", "fe_graph_launch",
-           "fe_graph_destroy", "fe_last_error")
+           "fe_graph_destroy", "fe_advance_noalloc", "fe_last_error")
 
 
 class FeError(RuntimeError):
@@ -96,6 +96,8 @@ def library():
         lib.fe_advance_workspace_size.restype = i32
         lib.fe_advance.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, pi, i32, vp, sz, vp]
         lib.fe_advance.restype = i32
+        lib.fe_advance_noalloc.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, pi, i32, vp]
+        lib.fe_advance_noalloc.restype = i32
         lib.fe_end.argtypes = [vp, ctypes.POINTER(_Job), pp, pi, i32, vp]
         lib.fe_end.restype = i32
         lib.fe_binned_workspace_size.argtypes = [vp, ctypes.POINTER(_Job), i32,
@@ -345,6 +347,15 @@ class Batch:
         _check(library().fe_advance(self.prior.handle, self.arr, self._sp, self.done, cnt,
                                     self.n, _ptr(self.ws), self.ws.numel(),
                                     _stream_handle(self.stream)))
+        for i in range(self.n):
+            self.done[i] += cnt[i]
+
+    def advance_noalloc(self, counts):
+        """advance() through fe_advance_noalloc: the job table goes to the
+        library's static device array instead of this batch's workspace."""
+        cnt = (ctypes.c_int32 * max(1, self.n))(*[int(c) for c in counts])
+        _check(library().fe_advance_noalloc(self.prior.handle, self.arr, self._sp, self.done,
+                                            cnt, self.n, _stream_handle(self.stream)))
         for i in range(self.n):
             self.done[i] += cnt[i]
 

@@ -65,4 +65,14 @@ hipError_t launch_direct_adjoint_grad(const DeviceBank &bank, const float *psi,
                                       int data_term, int precision, hipStream_t s);
 int direct_forward_blocks(int H, int W);
 
+// ---- allocation-free stepping (fe_noalloc.hip) ----------------------------
+// Size of the file-scope device array that holds the job table of
+// fe_advance_noalloc (one copy per device, kept until the process ends).
+constexpr size_t kNoallocScratchBytes = 256 * 1024;
+// Resolves the array's address on `device`, which must be current; once per
+// device (later calls return at once).  Called by fe_create.
+hipError_t noalloc_setup(int device);
+// The array's device address on `device`, or NULL before noalloc_setup.
+void *noalloc_scratch(int device);
+
 }  // namespace fe

@@ -309,6 +309,9 @@ fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out)
         e = hipMemcpy(b.alpha, c->alpha.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = fe::fused_upload(c->taps.data(), c->alpha.data(), m, nf, &c->fused);
+    // the device address of fe_advance_noalloc's static job table (once
+    // per device, with the device current)
+    if (e == hipSuccess) e = fe::noalloc_setup(device);
     if (e != hipSuccess) {
         fe_status st = e == hipErrorOutOfMemory ? fail(FE_ERR_NOMEM, "device allocation failed")
                                                 : hip_fail(e, "fe_create upload");
@@ -424,6 +427,27 @@ fe_status fe_advance(const fe_ctx *c, const fe_job *jobs, float *const *states,
     DeviceGuard g(c->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     return enqueue_advance(c, jobs, states, done, count, n, workspace, (hipStream_t)hip_stream);
+}
+
+fe_status fe_advance_noalloc(const fe_ctx *c, const fe_job *jobs, float *const *states,
+                             const int32_t *done, const int32_t *count, int32_t n,
+                             void *hip_stream)
+{
+    fe_status st = check_batch(c, jobs, n);
+    if (st == FE_OK) st = check_states(jobs, states, n);
+    if (st != FE_OK || n == 0) return st;
+    if (!done || !count) return fail(FE_ERR_INVALID, "done and count must be non-NULL");
+    for (int i = 0; i < n; ++i)
+        if (done[i] < 0 || count[i] < 0)
+            return fail(FE_ERR_INVALID, "job %d: negative done or count", i);
+    if (n > FE_NOALLOC_MAX_JOBS || fe::fused_table_bytes(n) > fe::kNoallocScratchBytes)
+        return fail(FE_ERR_INVALID, "fe_advance_noalloc: %d jobs exceed the static job table "
+                                    "(at most %d jobs)", n, FE_NOALLOC_MAX_JOBS);
+    void *table = fe::noalloc_scratch(c->device);
+    if (!table) return fail(FE_ERR_DEVICE, "static job table not set up on device %d", c->device);
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return enqueue_advance(c, jobs, states, done, count, n, table, (hipStream_t)hip_stream);
 }
 
 fe_status fe_end(const fe_ctx *c, const fe_job *jobs, float *const *states,
