@@ -100,11 +100,10 @@ def cpu_baseline(args, k, a, job, tau, gamma, gpu=None):
     if gpu and its == job.iterations:
         acc = accuracy(gpu, uo, xo, clean, job.peak)
     px_it = job.height * job.width * its
-    # the same oracle on one host thread, on a 256 x 256 crop for 20 iterations
+    # the same image and iterations on one host thread
     oracle.set_threads(1)
-    crop = np.ascontiguousarray(y[:256, :256])
     t1 = time.perf_counter()
-    oracle.denoise(crop, k, a, job.lam, tau, gamma, 20, job.data_term)
+    oracle.denoise(y, k, a, job.lam, tau, gamma, its, job.data_term)
     dt1 = time.perf_counter() - t1
     # the oracle-size case (64 x 64, peak 4, 24 filters of 5 x 5, 100 iterations)
     from synth.workloads import oracle_config, prior_for, step_size_for
@@ -132,9 +131,11 @@ def cpu_baseline(args, k, a, job, tau, gamma, gpu=None):
                       % (job.height, job.width, job.peak, its, k.shape[0], k.shape[1],
                          k.shape[2]),
             "cpu_model": model,
-            "single_core": {"value": crop.size * 20 / dt1 / 1e6, "unit": "Mpixel-iter/s",
+            "single_core": {"value": px_it / dt1 / 1e6, "unit": "Mpixel-iter/s",
                             "cores": 1, "seconds": dt1,
-                            "sample": "256x256 crop of the same image, 20 iterations"},
+                            "images_per_s": 1.0 / dt1,
+                            "sample": "the same image and iterations on one thread"},
+            "images_per_s": 1.0 / dt,
             "oracle_size_case": dict(small_rates, unit="Mpixel-iter/s",
                                      sample="64x64, peak 4, 24 5x5 filters, 100 iterations"),
             "accuracy": acc}
@@ -259,67 +260,68 @@ def batch_report(fe, torch, prior, args, tau, gamma, log=None):
 
 
 def energy_report(fe, torch, prior, cfg, counts, stream, reps=10):
-    """fe_energy_grad (the energy and its gradient, off the per-iteration
-    path) on the four images of the workload at u = v (the Anscombe-domain
-    start): gradient only (asynchronous, HIP events) and energy + gradient
-    (the energy returns to the host, so each call synchronises; wall clock).
-    Work per pixel: both filter banks, 2 * 2 * N_f * m^2 flops, and the psi
-    planes written and read back through HBM (2 * 4 * N_f bytes) plus u, y
-    and the gradient (12 bytes)."""
+    """fe_energy_grad_batch (the energy and its gradient, off the
+    per-iteration path) over the four images of the workload in one call, at
+    u = v (the Anscombe-domain start): gradient only (asynchronous, HIP events
+    around `reps` calls) and energy + gradient (the energies return to the
+    host, so each call synchronises; wall clock).  Algorithmic work per
+    pixel: both filter banks, 2 * 2 * N_f * m^2 flops; HBM: read u and y,
+    write the gradient, 12 bytes."""
     import ctypes
     lib = fe.library()
     m, nf = cfg["m"], cfg["n_filters"]
     H, W = counts[0].shape
-    px = H * W
+    n = len(counts)
+    px = H * W * n
     us = [2.0 * torch.sqrt(c + 0.375) for c in counts]
     grads = [torch.empty_like(u) for u in us]
+    arr = (fe._GradJob * n)()
+    for i, (c, u, g, j) in enumerate(zip(counts, us, grads, cfg["jobs"])):
+        arr[i] = fe._GradJob(H, W, c.data_ptr(), u.data_ptr(), g.data_ptr(), float(j.lam),
+                             int(j.data_term))
     sz = ctypes.c_size_t()
-    st = lib.fe_energy_grad_workspace_size(prior.handle, H, W, ctypes.byref(sz))
+    st = lib.fe_energy_grad_batch_workspace_size(prior.handle, arr, n, ctypes.byref(sz))
     if st != 0:
         raise fe.FeError(st, lib.fe_last_error().decode())
     ws = fe.alloc_workspace(sz.value, "cuda")
     flop_px = flops_per_px_it(m, nf)
-    bytes_px = 2 * 4 * nf + 12
-    out = {"workload": "%d images of %dx%d, %d %dx%d filters, u = v" % (len(counts), H, W,
-                                                                        nf, m, m),
+    bytes_px = 12
+    out = {"workload": "%d images of %dx%d in one call, %d %dx%d filters, u = v"
+                       % (n, H, W, nf, m, m),
            "flop_per_px": flop_px, "hbm_bytes_per_px": bytes_px}
-    for prec in ("fp32", "bf16"):
+    en = (ctypes.c_double * n)()
+    for prec in ("fp32", "bf16", "fp16"):
         pr = fe._PREC[prec]
-        e = ctypes.c_double()
 
-        def call(i, want_energy):
-            j = cfg["jobs"][i]
-            r = lib.fe_energy_grad(prior.handle, H, W, fe._ptr(counts[i]), fe._ptr(us[i]),
-                                   float(j.lam), int(j.data_term), pr,
-                                   ctypes.byref(e) if want_energy else None,
-                                   fe._ptr(grads[i]), fe._ptr(ws), ws.numel(),
-                                   fe._stream_handle(stream))
+        def call(want_energy):
+            r = lib.fe_energy_grad_batch(prior.handle, arr, n, pr,
+                                         en if want_energy else None, fe._ptr(ws), ws.numel(),
+                                         fe._stream_handle(stream))
             if r != 0:
                 raise fe.FeError(r, lib.fe_last_error().decode())
 
-        for i in range(len(counts)):
-            call(i, True)
+        call(True)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(reps):
-            for i in range(len(counts)):
-                call(i, False)
+            call(False)
         ev1.record(stream)
         torch.cuda.synchronize()
-        ms_grad = ev0.elapsed_time(ev1) / (reps * len(counts))
+        ms_grad = ev0.elapsed_time(ev1) / reps
         t0 = time.perf_counter()
         for _ in range(reps):
-            for i in range(len(counts)):
-                call(i, True)
-        ms_both = (time.perf_counter() - t0) * 1e3 / (reps * len(counts))
-        out[prec] = {"grad_ms_per_image": round(ms_grad, 4),
-                     "energy_grad_ms_per_image": round(ms_both, 4),
+            call(True)
+        ms_both = (time.perf_counter() - t0) * 1e3 / reps
+        peak = FP32_PEAK_TFLOPS if prec == "fp32" else MFMA16_PEAK_TFLOPS
+        ach = flop_px * px / (ms_grad * 1e-3) / 1e12
+        out[prec] = {"grad_ms_per_call": round(ms_grad, 4),
+                     "energy_grad_ms_per_call": round(ms_both, 4),
                      "grad_Mpixel_per_s": round(px / (ms_grad * 1e-3) / 1e6, 1),
-                     "achieved_TFLOPs": round(flop_px * px / (ms_grad * 1e-3) / 1e12, 3),
-                     "frac_of_fp32_vector_peak": round(flop_px * px / (ms_grad * 1e-3) / 1e12
-                                                       / FP32_PEAK_TFLOPS, 4),
+                     "achieved_TFLOPs": round(ach, 3),
+                     "frac_of_matrix_peak": round(ach / peak, 4),
+                     "matrix_peak_TFLOPs": peak,
                      "hbm_algorithmic_GBs": round(bytes_px * px / (ms_grad * 1e-3) / 1e9, 1)}
     del ws, us, grads
     return out
@@ -390,9 +392,11 @@ def main():
     ap.add_argument("--batch-precisions", default="fp32,bf16")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the one-image-per-call form of the batch section")
-    ap.add_argument("--serving-requests", type=int, default=200,
-                    help="requests per serving run (the full serving workload "
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests per serving run (the full 10,000-request workload "
                          "is python -m paper_1609_05722_amd.serving)")
+    ap.add_argument("--serving-loads", default="0.5,0.75,0.9",
+                    help="offered loads, fractions of each form's own saturation rate")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the bf16 / fp16 contraction timings")
     ap.add_argument("--no-energy", action="store_true",
@@ -525,7 +529,10 @@ def main():
 
     def serving_section():
         from paper_1609_05722_amd.serving import serving_report
-        return serving_report(prior, args.serving_requests, (0.5, 0.9), "bf16")
+        loads = tuple(float(x) for x in args.serving_loads.split(","))
+        return serving_report(prior, args.serving_requests, loads, "bf16",
+                              same_rate_loads=(0.9,),
+                              log=lambda t: print(t, file=sys.stderr, flush=True))
 
     def cpu_section():
         job4 = [j for j in cfg["jobs"] if j.peak == 4.0][0]

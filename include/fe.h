@@ -223,11 +223,16 @@ fe_status fe_denoise_binned(const fe_ctx *ctx, const fe_job *jobs, int32_t n,
 /* ---- continuous-batching server -----------------------------------------
  * A worker thread admits submitted jobs in arrival order as device memory
  * (a budget allocated once at create) frees up, keeps each admitted job's
- * state resident, and runs ticks: every tick advances every resident job by
- * up to iters_per_tick iterations in shared launches (fe_advance), starts
- * newly admitted jobs (fe_begin) and finishes completed ones (fe_end).
- * Results are bitwise those of fe_denoise on the job alone.  The client
- * owns each job's counts and output buffers until its completion is polled. */
+ * state resident, and runs ticks: every tick advances the resident jobs by
+ * up to iters_per_tick iterations each in shared launches (fe_advance),
+ * starts newly admitted jobs (fe_begin) and finishes completed ones
+ * (fe_end).  With tick_pixel_iters > 0 a tick offers its iterations to the
+ * resident jobs oldest first and stops once it holds that many
+ * pixel-iterations (the oldest job always advances), which bounds a tick's
+ * duration and lets the oldest jobs finish first; with 0 every resident job
+ * advances every tick.  Results are bitwise those of fe_denoise on the job
+ * alone.  The client owns each job's counts and output buffers until its
+ * completion is polled. */
 typedef struct fe_server fe_server;
 
 typedef struct {
@@ -235,6 +240,7 @@ typedef struct {
     int32_t iters_per_tick;   /* iterations per resident job per tick, >= 1   */
     int32_t max_active;       /* most jobs resident at once, >= 1             */
     int32_t ticks_in_flight;  /* ticks enqueued ahead of the device, 1..64    */
+    int64_t tick_pixel_iters; /* work per tick (0: no limit), >= 0            */
 } fe_server_config;
 
 typedef struct {
@@ -266,26 +272,58 @@ void fe_server_destroy(fe_server *srv);
 /* Message for the last non-OK status of a server call on this thread. */
 const char *fe_server_last_error(void);
 
-/* Workspace bytes fe_energy_grad needs for an H x W image. */
+/* Workspace bytes fe_energy_grad needs for an H x W image (H * W < 2^31):
+ * the launch's job table and two partial sums per workgroup tile. */
 fe_status fe_energy_grad_workspace_size(const fe_ctx *ctx, int32_t height,
                                         int32_t width, size_t *bytes);
 
 /* Energy E(u) = E_FoE(u) + D(u, v) (eq. 2.5 with eq. 3.4 or 3.6) and its
- * gradient, at an Anscombe-domain image u (DEVICE H*W) for counts y
- * (DEVICE H*W, v = f_A(y)).  data_term is FE_DATA_QUADRATIC or
- * FE_DATA_IDIV.  precision (FE_PREC_*) rounds the operands of both
- * filter-bank contractions (u and k_i for K_i u; psi_i and k_i for
- * K_i^T psi_i) to that format, products accumulated in FP32; the influence,
- * log(1 + z^2) and the data term stay FP32.  If `energy` (HOST) is not NULL
- * the call synchronises the stream and stores E there; with the I-divergence
- * term E is +inf when any u <= 0.  If `grad` (DEVICE H*W) is not NULL it
- * receives grad E.  Sums are accumulated in FP32 per workgroup and combined
- * in FP64 in a fixed order, so the result is deterministic. */
+ * gradient grad E(u) = sum_i alpha_i K_i^T rho'(K_i u) + grad D (eq. 3.2),
+ * at an Anscombe-domain image u (DEVICE H*W) for counts y (DEVICE H*W,
+ * v = f_A(y)).  data_term is FE_DATA_QUADRATIC or FE_DATA_IDIV.  One fused
+ * launch over the image's tiles, as the denoising step: the filter
+ * responses stay on chip.  precision (FE_PREC_*) selects the contractions'
+ * operands as in the denoising step: BF16 / FP16 round u and k_i in K_i u,
+ * and z_i / (1 + z_i^2) and 2 alpha_i k_i in the adjoint, products
+ * accumulated in FP32; the influence, rho(z) = log(1 + z^2) and the data
+ * term stay FP32.  If `energy` (HOST) is not NULL the call synchronises the
+ * stream and stores E there; with the I-divergence term E is +inf when any
+ * u <= 0.  If `grad` (DEVICE H*W) is not NULL it receives grad E.  Energy
+ * sums: FP32 per workgroup over the pixels its tile owns, then FP64 over
+ * the workgroups in a fixed order on the device, so the result is
+ * deterministic.  The workspace (DEVICE, 256-byte aligned) must not be
+ * reused until the stream has passed the call.  This is
+ * fe_energy_grad_batch on one image. */
 fe_status fe_energy_grad(const fe_ctx *ctx, int32_t height, int32_t width,
                          const float *counts, const float *u, float lambda,
                          int32_t data_term, int32_t precision, double *energy,
                          float *grad, void *workspace, size_t ws_bytes,
                          void *hip_stream);
+
+/* One image of fe_energy_grad_batch (the arguments of fe_energy_grad). */
+typedef struct {
+    int32_t height, width;  /* each >= r; H * W < 2^31                       */
+    const float *counts;    /* DEVICE H*W, y >= 0                            */
+    const float *u;         /* DEVICE H*W, Anscombe-domain image             */
+    float *grad;            /* DEVICE H*W, receives grad E(u); may be NULL   */
+    float lambda;           /* data-term weight, > 0                         */
+    int32_t data_term;      /* FE_DATA_QUADRATIC or FE_DATA_IDIV             */
+} fe_grad_job;
+
+/* Workspace bytes fe_energy_grad_batch needs for these images. */
+fe_status fe_energy_grad_batch_workspace_size(const fe_ctx *ctx, const fe_grad_job *jobs,
+                                              int32_t n, size_t *bytes);
+
+/* fe_energy_grad over n images in one launch (every tile of every image
+ * shares it, as the denoising step's batches do): energies (HOST [n] or
+ * NULL; if not NULL the call synchronises the stream) receives E of each
+ * image, each job's grad (if not NULL) its gradient; contractions in
+ * `precision` for every image.  Each image's gradient is bitwise that of
+ * fe_energy_grad on it alone; its energy agrees to the rounding of the
+ * FP32 per-tile sums (the tile height is chosen for the whole batch). */
+fe_status fe_energy_grad_batch(const fe_ctx *ctx, const fe_grad_job *jobs, int32_t n,
+                               int32_t precision, double *energies, void *workspace,
+                               size_t ws_bytes, void *hip_stream);
 
 /* Release the context (NULL is allowed). */
 void fe_destroy(fe_ctx *ctx);

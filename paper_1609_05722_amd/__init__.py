@@ -9,6 +9,7 @@ Entry points mirror include/fe.h:
   Prior(filters, weights, device=0)      fe_create / fe_destroy
   denoise(counts, prior, ...)            fe_denoise (one or many jobs)
   energy_grad(counts, u, prior, ...)     fe_energy_grad
+  energy_grad_batch(items, prior, ...)   fe_energy_grad_batch
 """
 import ctypes
 import os
@@ -29,6 +30,7 @@ EXPORTS = ("fe_create", "fe_destroy", "fe_workspace_size", "fe_denoise",
            "fe_state_bytes", "fe_begin", "fe_advance_workspace_size", "fe_advance",
            "fe_end", "fe_binned_workspace_size", "fe_denoise_binned",
            "fe_energy_grad_workspace_size", "fe_energy_grad",
+           "fe_energy_grad_batch_workspace_size", "fe_energy_grad_batch",
            "fe_server_create", "fe_server_submit", "fe_server_poll", "fe_server_load",
            "fe_server_destroy", "fe_server_last_error", "fe_autotune", "fe_tuning_save",
            "fe_tuning_load", "fe_advance_graph_create", "fe_graph_launch",
@@ -54,6 +56,13 @@ class _Job(ctypes.Structure):
                 ("iterations", ctypes.c_int32), ("data_term", ctypes.c_int32),
                 ("peak", ctypes.c_float), ("tau", ctypes.c_float),
                 ("gamma", ctypes.c_float), ("precision", ctypes.c_int32)]
+
+
+class _GradJob(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("counts", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("lambda_", ctypes.c_float),
+                ("data_term", ctypes.c_int32)]
 
 
 _lib = None
@@ -86,6 +95,12 @@ def library():
         lib.fe_energy_grad.argtypes = [vp, i32, i32, vp, vp, ctypes.c_float, i32, i32,
                                        ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
         lib.fe_energy_grad.restype = i32
+        lib.fe_energy_grad_batch_workspace_size.argtypes = [vp, ctypes.POINTER(_GradJob), i32,
+                                                            ctypes.POINTER(sz)]
+        lib.fe_energy_grad_batch_workspace_size.restype = i32
+        lib.fe_energy_grad_batch.argtypes = [vp, ctypes.POINTER(_GradJob), i32, i32,
+                                             ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+        lib.fe_energy_grad_batch.restype = i32
         pp = ctypes.POINTER(ctypes.c_void_p)
         pi = ctypes.POINTER(ctypes.c_int32)
         lib.fe_state_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
@@ -313,6 +328,37 @@ def energy_grad(counts, u, prior, lam, data_term, want_energy=True,
                                     _ptr(grad), _ptr(ws), ws.numel(),
                                     _stream_handle(stream)))
     return (e.value if want_energy else None), grad
+
+
+def energy_grad_batch(items, prior, want_energy=True, want_grad=True, stream=None,
+                      precision="fp32"):
+    """fe_energy_grad_batch: items = [(counts, u, lam, data_term), ...] (CUDA
+    tensors).  Returns (list of energies or None, list of gradients or
+    None); one launch over every image."""
+    torch = _torch()
+    n = len(items)
+    arr = (_GradJob * max(1, n))()
+    grads = []
+    for i, (c, u, lam, dt) in enumerate(items):
+        c = _device_f32(c, "counts")
+        u = _device_f32(u, "u")
+        H, W = c.shape
+        g = torch.empty_like(u) if want_grad else None
+        grads.append(g)
+        d = _DATA[dt] if isinstance(dt, str) else int(dt)
+        arr[i] = _GradJob(H, W, c.data_ptr(), u.data_ptr(),
+                          g.data_ptr() if g is not None else None, float(lam), d)
+    sz = ctypes.c_size_t()
+    _check(library().fe_energy_grad_batch_workspace_size(prior.handle, arr, n,
+                                                         ctypes.byref(sz)))
+    ws = alloc_workspace(sz.value, items[0][0].device if n else "cuda")
+    en = (ctypes.c_double * max(1, n))()
+    pr = _PREC[precision] if isinstance(precision, str) else int(precision)
+    _check(library().fe_energy_grad_batch(prior.handle, arr, n, pr,
+                                          en if want_energy else None, _ptr(ws), ws.numel(),
+                                          _stream_handle(stream)))
+    return ([en[i] for i in range(n)] if want_energy else None), \
+        (grads if want_grad else None)
 
 
 class Batch:

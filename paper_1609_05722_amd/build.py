@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfe.so")
 SOURCES = ["fe_runtime.cpp", "fe_server.cpp", "fe_noalloc.hip", "kernels_pointwise.hip",
-           "kernels_direct.hip", "kernels_fused.hip"]
+           "kernels_fused.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

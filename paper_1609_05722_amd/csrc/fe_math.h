@@ -40,6 +40,25 @@ __device__ __forceinline__ float anscombe_fast(float y)
     return 2.0f * __builtin_amdgcn_sqrtf(y + 0.375f);
 }
 
+// Student-t potential rho(z) = log(1 + z^2) (eq. 2.6).  With x = z^2:
+// below 1/16 the series x - x^2/2 + ... + x^5/5 - x^6/6 (truncation below
+// x^7/7, a relative 1e-8), so that small responses keep their relative
+// accuracy; above, ln 2 * log2(1 + x) on the hardware logarithm, whose
+// result is then at least 0.087 and whose rounding of 1 + x costs at most
+// 2^-24 relative.  Branch-free.
+__device__ __forceinline__ float student_t_rho(float z)
+{
+    const float x = z * z;
+    float s = fmaf(x, -1.0f / 6.0f, 0.2f);
+    s = fmaf(x, s, -0.25f);
+    s = fmaf(x, s, 1.0f / 3.0f);
+    s = fmaf(x, s, -0.5f);
+    s = fmaf(x, s, 1.0f);
+    const float series = x * s;
+    const float lg = 0.693147181f * __builtin_amdgcn_logf(1.0f + x);
+    return x < 0.0625f ? series : lg;
+}
+
 // Data-term energy per pixel without the lambda factor:
 //  quadratic 1/2 (u - v)^2; I-divergence u - v log u (+inf for u <= 0).
 __device__ __forceinline__ float data_energy(float u, float v, int data_term)

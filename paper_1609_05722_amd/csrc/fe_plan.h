@@ -27,6 +27,7 @@ struct FusedBank {
     float *lasta = nullptr;      // last tap x 2alpha, adjoint  [nfb][4][64]
     void *bf_fwd = nullptr, *bf_adj = nullptr;  // bfloat16 operand tables
     void *h_fwd = nullptr, *h_adj = nullptr;    // float16 operand tables
+    float *alpha = nullptr;      // alpha_i, zero-padded to 64 (energy)
 };
 
 // How a batch is cut into workgroup tiles: every job's image is split into
@@ -102,5 +103,23 @@ size_t fused_table_bytes(int n);
 hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, void *plan_ws,
                      hipStream_t s, const TuneTable *tune = nullptr, int only_prec = -1,
                      TileChoice forced = TileChoice{});
+
+// One image of a gradient launch: grad E(u) (eq. 3.2 plus the data term's
+// gradient) into grad (NULL: not stored), E(u) (eq. 2.5 with eq. 3.4 / 3.6)
+// on request.
+struct GradItem {
+    int height, width;
+    const float *counts, *u;
+    float *grad;
+    float lambda;
+    int data_term;   // FE_DATA_QUADRATIC or FE_DATA_IDIV
+};
+// One fused launch over every tile of the images (contractions in precision
+// prec); with `energy`, the energies are summed by a second, deterministic
+// pass into n device doubles whose address goes to *energy_dev.  ws:
+// DEVICE, 256-byte aligned, grad_workspace_bytes.
+size_t grad_workspace_bytes(const FusedBank &bank, const GradItem *items, int n);
+hipError_t run_grad(const FusedBank &bank, const GradItem *items, int n, int prec, bool energy,
+                    void *ws, double **energy_dev, hipStream_t s);
 
 }  // namespace fe

@@ -24,7 +24,6 @@ struct fe_ctx {
     int device = 0;
     int m = 0, nf = 0;
     std::vector<float> taps, alpha;  // host copies
-    fe::DeviceBank bank;
     fe::FusedBank fused;             // matrix-core operand tables
     mutable fe::TuneTable tune;      // measured tile shapes (internally locked)
 };
@@ -278,37 +277,7 @@ fe_status fe_create(const fe_prior *prior, int device, fe_ctx **out)
         delete c;
         return hip_fail(g.err, "hipSetDevice");
     }
-    std::vector<float> a2(nf);
-    for (int i = 0; i < nf; ++i) a2[i] = 2.0f * c->alpha[i];
-    fe::DeviceBank &b = c->bank;
-    b.m = m;
-    b.nf = nf;
-    // the taps rounded once to BF16 and FP16 (nearest even), for the direct
-    // kernels' reduced-precision contractions
-    const size_t nt = (size_t)nf * m * m;
-    std::vector<float> tr[2] = {std::vector<float>(nt), std::vector<float>(nt)};
-    for (size_t i = 0; i < nt; ++i) {
-        uint32_t w;
-        std::memcpy(&w, &c->taps[i], 4);
-        w = (w + 0x7FFFu + ((w >> 16) & 1u)) & 0xFFFF0000u;
-        std::memcpy(&tr[0][i], &w, 4);
-        tr[1][i] = (float)(_Float16)c->taps[i];
-    }
-    hipError_t e = hipMalloc((void **)&b.taps, sizeof(float) * nt);
-    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
-        e = hipMalloc((void **)&b.taps_r[r], sizeof(float) * nt);
-        if (e == hipSuccess)
-            e = hipMemcpy(b.taps_r[r], tr[r].data(), sizeof(float) * nt, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) e = hipMalloc((void **)&b.alpha2, sizeof(float) * nf);
-    if (e == hipSuccess) e = hipMalloc((void **)&b.alpha, sizeof(float) * nf);
-    if (e == hipSuccess)
-        e = hipMemcpy(b.taps, c->taps.data(), sizeof(float) * nf * m * m, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b.alpha2, a2.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(b.alpha, c->alpha.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = fe::fused_upload(c->taps.data(), c->alpha.data(), m, nf, &c->fused);
+    hipError_t e = fe::fused_upload(c->taps.data(), c->alpha.data(), m, nf, &c->fused);
     // the device address of fe_advance_noalloc's static job table (once
     // per device, with the device current)
     if (e == hipSuccess) e = fe::noalloc_setup(device);
@@ -326,11 +295,6 @@ void fe_destroy(fe_ctx *c)
 {
     if (!c) return;
     DeviceGuard g(c->device);
-    (void)hipFree(c->bank.taps);
-    (void)hipFree(c->bank.taps_r[0]);
-    (void)hipFree(c->bank.taps_r[1]);
-    (void)hipFree(c->bank.alpha2);
-    (void)hipFree(c->bank.alpha);
     fe::fused_release(&c->fused);
     delete c;
 }
@@ -719,17 +683,110 @@ void fe_graph_destroy(fe_graph *gr)
     delete gr;
 }
 
+}  // extern "C"
+
+namespace {
+
+fe_status check_grad_jobs(const fe_ctx *c, const fe_grad_job *jobs, int32_t n)
+{
+    if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(FE_ERR_INVALID, "negative job count");
+    if (n > 0 && !jobs) return fail(FE_ERR_INVALID, "jobs is NULL");
+    const int r = radius(c);
+    for (int i = 0; i < n; ++i) {
+        const fe_grad_job &j = jobs[i];
+        if (j.height < 1 || j.width < 1 || j.height < r || j.width < r)
+            return fail(FE_ERR_INVALID, "job %d: image %dx%d smaller than the filter radius %d",
+                        i, j.height, j.width, r);
+        if ((long long)j.height * j.width > (1LL << 31) - 1)
+            return fail(FE_ERR_INVALID, "job %d: image too large", i);
+        if (!j.counts || !j.u) return fail(FE_ERR_INVALID, "job %d: counts and u must be non-NULL", i);
+        if (!(j.lambda > 0.0f) || !std::isfinite(j.lambda))
+            return fail(FE_ERR_INVALID, "job %d: lambda must be finite and > 0", i);
+        if (j.data_term != FE_DATA_QUADRATIC && j.data_term != FE_DATA_IDIV)
+            return fail(FE_ERR_INVALID, "job %d: data term must be FE_DATA_QUADRATIC or "
+                                        "FE_DATA_IDIV", i);
+    }
+    return FE_OK;
+}
+
+std::vector<fe::GradItem> grad_items(const fe_grad_job *jobs, int32_t n)
+{
+    std::vector<fe::GradItem> it(n);
+    for (int i = 0; i < n; ++i)
+        it[i] = {jobs[i].height, jobs[i].width, jobs[i].counts, jobs[i].u, jobs[i].grad,
+                 jobs[i].lambda, jobs[i].data_term};
+    return it;
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_energy_grad_batch_workspace_size(const fe_ctx *c, const fe_grad_job *jobs,
+                                              int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    fe_status st = check_grad_jobs(c, jobs, n);
+    if (st != FE_OK) return st;
+    std::vector<fe::GradItem> it = grad_items(jobs, n);
+    *bytes = fe::grad_workspace_bytes(c->fused, it.data(), n);
+    return FE_OK;
+}
+
+fe_status fe_energy_grad_batch(const fe_ctx *c, const fe_grad_job *jobs, int32_t n,
+                               int32_t precision, double *energies, void *workspace,
+                               size_t ws_bytes, void *hip_stream)
+{
+    fe_status st = check_grad_jobs(c, jobs, n);
+    if (st != FE_OK) return st;
+    if (precision < FE_PREC_FP32 || precision > FE_PREC_FP16)
+        return fail(FE_ERR_INVALID, "precision %d is not an FE_PREC_* value", precision);
+    std::vector<fe::GradItem> it = grad_items(jobs, n);
+    st = check_workspace(workspace, ws_bytes, fe::grad_workspace_bytes(c->fused, it.data(), n));
+    if (st != FE_OK) return st;
+    bool any_grad = false;
+    for (int i = 0; i < n; ++i) any_grad = any_grad || jobs[i].grad;
+    if (n == 0 || (!energies && !any_grad)) return FE_OK;
+
+    DeviceGuard g(c->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    {
+        std::vector<const float *> planes(n);
+        std::vector<long> sizes(n);
+        for (int i = 0; i < n; ++i) {
+            planes[i] = jobs[i].counts;
+            sizes[i] = (long)jobs[i].height * jobs[i].width;
+        }
+        st = validate_counts(planes.data(), sizes.data(), n, s);
+        if (st != FE_OK) return st;
+    }
+    double *edev = nullptr;
+    hipError_t e = fe::run_grad(c->fused, it.data(), n, precision, energies != nullptr,
+                                workspace, &edev, s);
+    if (e != hipSuccess) return hip_fail(e, "energy / gradient launch");
+    if (energies) {
+        e = hipMemcpyAsync(energies, edev, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "energy readback");
+    }
+    return FE_OK;
+}
+
 fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)
 {
+    fe_grad_job j{H, W, nullptr, nullptr, nullptr, 1.0f, FE_DATA_QUADRATIC};
     if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
     *bytes = 0;
     if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
     const int r = radius(c);
     if (H < 1 || W < 1 || H < r || W < r)
         return fail(FE_ERR_INVALID, "image %dx%d smaller than the filter radius %d", H, W, r);
-    const size_t plane = (size_t)H * W * sizeof(float);
-    const size_t nb = (size_t)fe::direct_forward_blocks(H, W);
-    *bytes = align256(plane * c->nf) + 2 * align256(nb * sizeof(float));
+    if ((long long)H * W > (1LL << 31) - 1) return fail(FE_ERR_INVALID, "image too large");
+    fe::GradItem it{j.height, j.width, nullptr, nullptr, nullptr, 1.0f, FE_DATA_QUADRATIC};
+    *bytes = fe::grad_workspace_bytes(c->fused, &it, 1);
     return FE_OK;
 }
 
@@ -738,59 +795,8 @@ fe_status fe_energy_grad(const fe_ctx *c, int32_t H, int32_t W, const float *cou
                          double *energy, float *grad, void *workspace, size_t ws_bytes,
                          void *hip_stream)
 {
-    size_t need = 0;
-    fe_status st = fe_energy_grad_workspace_size(c, H, W, &need);
-    if (st != FE_OK) return st;
-    if (!counts || !u) return fail(FE_ERR_INVALID, "counts and u must be non-NULL");
-    if (!(lambda > 0.0f) || !std::isfinite(lambda))
-        return fail(FE_ERR_INVALID, "lambda must be finite and > 0");
-    if (data_term != FE_DATA_QUADRATIC && data_term != FE_DATA_IDIV)
-        return fail(FE_ERR_INVALID, "data term must be FE_DATA_QUADRATIC or FE_DATA_IDIV");
-    if (precision < FE_PREC_FP32 || precision > FE_PREC_FP16)
-        return fail(FE_ERR_INVALID, "precision %d is not an FE_PREC_* value", precision);
-    if (!workspace || ((uintptr_t)workspace & 255))
-        return fail(FE_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
-    if (ws_bytes < need) return fail(FE_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, need);
-    if (!energy && !grad) return FE_OK;
-
-    DeviceGuard g(c->device);
-    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipStream_t s = (hipStream_t)hip_stream;
-    {
-        const long np = (long)H * W;
-        st = validate_counts(&counts, &np, 1, s);
-        if (st != FE_OK) return st;
-    }
-    char *ws = (char *)workspace;
-    const size_t plane = (size_t)H * W * sizeof(float);
-    float *psi = (float *)ws;
-    const int nb = fe::direct_forward_blocks(H, W);
-    float *rho_part = (float *)(ws + align256(plane * c->nf));
-    float *data_part = (float *)(ws + align256(plane * c->nf) + align256(nb * sizeof(float)));
-    int nblocks = 0;
-    hipError_t e = fe::launch_direct_forward(c->bank, u, H, W, psi, energy ? rho_part : nullptr,
-                                             energy ? data_part : nullptr, counts, lambda,
-                                             data_term, precision, &nblocks, s);
-    if (e != hipSuccess) return hip_fail(e, "energy forward");
-    if (grad) {
-        e = fe::launch_direct_adjoint_grad(c->bank, psi, u, counts, grad, H, W, lambda,
-                                           data_term, precision, s);
-        if (e != hipSuccess) return hip_fail(e, "energy adjoint");
-    }
-    if (energy) {
-        std::vector<float> hr(nblocks), hd(nblocks);
-        e = hipMemcpyAsync(hr.data(), rho_part, sizeof(float) * nblocks, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hd.data(), data_part, sizeof(float) * nblocks,
-                               hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "energy readback");
-        double sum = 0.0;
-        for (int b = 0; b < nblocks; ++b) sum += (double)hr[b];
-        for (int b = 0; b < nblocks; ++b) sum += (double)hd[b];
-        *energy = sum;
-    }
-    return FE_OK;
+    const fe_grad_job j{H, W, counts, u, grad, lambda, data_term};
+    return fe_energy_grad_batch(c, &j, 1, precision, energy, workspace, ws_bytes, hip_stream);
 }
 
 }  // extern "C"

@@ -80,6 +80,7 @@ class Arena {
 struct SchedJob {
     uint64_t id = 0;     // server-assigned, increasing in submission order
     size_t bytes = 0;    // device memory the job holds while resident
+    long px = 0;         // pixels of the image (work per iteration)
     int total = 0;       // iterations requested
     int done = 0;        // iterations enqueued so far
     size_t off = 0;      // arena offset once admitted
@@ -96,22 +97,31 @@ struct TickPlan {
     std::vector<uint64_t> finishing;  // reach their total with this tick
 };
 
+// Admission is in arrival order (no overtaking).  Each tick offers every
+// resident job up to iters_per_tick iterations, oldest first; with a work
+// budget (tick_work > 0 pixel-iterations) the offer stops once the tick
+// holds that much work, so that a tick's duration stays bounded however
+// many jobs are resident and the oldest jobs finish first (the oldest
+// always advances, so every job finishes).  Without a budget every resident
+// job advances every tick (processor sharing).
 class Scheduler {
   public:
-    Scheduler(size_t budget, int iters_per_tick, int max_active)
+    Scheduler(size_t budget, int iters_per_tick, int max_active, long long tick_work = 0)
         : arena_(budget), per_tick_(std::max(1, iters_per_tick)),
-          max_active_(max_active > 0 ? max_active : 1 << 30)
+          max_active_(max_active > 0 ? max_active : 1 << 30),
+          tick_work_(tick_work > 0 ? tick_work : 0)
     {
     }
 
     // A job larger than the whole budget could never run.
     bool fits_ever(size_t bytes) const { return Arena::round(bytes) <= arena_.capacity(); }
 
-    uint64_t submit(size_t bytes, int total, double now)
+    uint64_t submit(size_t bytes, int total, double now, long px = 0)
     {
         SchedJob j;
         j.id = next_id_++;
         j.bytes = bytes;
+        j.px = px;
         j.total = std::max(0, total);
         j.t_submit = now;
         pending_.push_back(j);
@@ -119,8 +129,10 @@ class Scheduler {
     }
 
     // Admit in arrival order while memory and the active cap allow (the
-    // queue head blocks later arrivals: no overtaking), then give every
-    // resident job min(per_tick, remaining) iterations.
+    // queue head blocks later arrivals: no overtaking), then give the
+    // resident jobs, oldest first, min(per_tick, remaining) iterations each
+    // until the tick's work budget (if any) is spent; the rest get none
+    // this tick.
     TickPlan plan(double now)
     {
         TickPlan t;
@@ -135,8 +147,11 @@ class Scheduler {
             pending_.pop_front();
         }
         std::vector<SchedJob> keep;
+        long long work = 0;
         for (SchedJob &j : active_) {
-            const int c = std::min(per_tick_, j.total - j.done);
+            const bool spent = tick_work_ > 0 && work >= tick_work_;
+            const int c = spent ? 0 : std::min(per_tick_, j.total - j.done);
+            work += (long long)c * j.px;
             t.active.push_back(j.id);
             t.done_before.push_back(j.done);
             t.count.push_back(c);
@@ -183,6 +198,7 @@ class Scheduler {
   private:
     Arena arena_;
     int per_tick_, max_active_;
+    long long tick_work_;
     uint64_t next_id_ = 1;
     std::deque<SchedJob> pending_;
     std::vector<SchedJob> active_, retiring_;

@@ -1,8 +1,9 @@
 // Continuous-batching server over the stepping ABI (fe_begin / fe_advance /
 // fe_end).  Requests arrive at any time; a worker thread admits them in
 // arrival order as device memory frees up, keeps every admitted job's
-// state (u^n, u^{n-1}) resident, and runs ticks: each tick advances every
-// resident job by up to `iters_per_tick` iterations in shared launches, so
+// state (u^n, u^{n-1}) resident, and runs ticks: each tick advances the
+// resident jobs (oldest first, up to an optional work budget) by up to
+// `iters_per_tick` iterations each in shared launches, so
 // jobs of different sizes, iteration counts and precisions overlap on the
 // device.  A job's result is bitwise the one fe_denoise gives it alone (the
 // step's per-pixel arithmetic does not depend on the batch).
@@ -145,7 +146,8 @@ void fe_server::run()
             while (!incoming.empty()) {
                 Request r = incoming.front();
                 incoming.pop_front();
-                const uint64_t id = sched->submit(r.bytes, r.job.iterations, r.t_submit);
+                const uint64_t id = sched->submit(r.bytes, r.job.iterations, r.t_submit,
+                                                  (long)r.job.height * r.job.width);
                 jobs.emplace(id, r);
             }
             failed = status != FE_OK;
@@ -242,7 +244,7 @@ fe_status fe_server_create(const fe_ctx *ctx, const fe_server_config *cfg, void 
     *out = nullptr;
     if (!ctx || !cfg) return srv_fail(FE_ERR_INVALID, "ctx and cfg must be non-NULL");
     if (cfg->hbm_budget_bytes < 4096 || cfg->iters_per_tick < 1 || cfg->max_active < 1 ||
-        cfg->ticks_in_flight < 1 || cfg->ticks_in_flight > 64)
+        cfg->ticks_in_flight < 1 || cfg->ticks_in_flight > 64 || cfg->tick_pixel_iters < 0)
         return srv_fail(FE_ERR_INVALID, "bad server configuration");
     fe_server *s = new (std::nothrow) fe_server;
     if (!s) return srv_fail(FE_ERR_NOMEM, "host allocation failed");
@@ -280,7 +282,8 @@ fe_status fe_server_create(const fe_ctx *ctx, const fe_server_config *cfg, void 
         return srv_fail(e == hipErrorOutOfMemory ? FE_ERR_NOMEM : FE_ERR_DEVICE,
                         hipGetErrorString(e));
     }
-    s->sched = new fe::Scheduler(cfg->hbm_budget_bytes, cfg->iters_per_tick, cfg->max_active);
+    s->sched = new fe::Scheduler(cfg->hbm_budget_bytes, cfg->iters_per_tick, cfg->max_active,
+                                 cfg->tick_pixel_iters);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return FE_OK;

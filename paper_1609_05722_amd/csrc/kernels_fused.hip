@@ -92,8 +92,19 @@ struct JobDesc {
     int it0;            // iterations already applied (parity of the state)
     float tau, gamma, tl;
     float q1;           // 1 / (1 + tl)
+    float lambda;       // data-term weight (the gradient modes)
     int data_term;
 };
+
+// What a launch of the fused kernel computes per output pixel:
+//   kStep:       one iPiano iteration (eq. 2.8), u^{n+1} over u^{n-1};
+//   kGrad:       grad E(u) = sum_i alpha_i K_i^T rho'(K_i u) + grad D(u, v)
+//                (eq. 3.2 with the data term of eq. 3.4 / 3.6) into ub;
+//   kGradEnergy: the same, plus the workgroup's partial sums of the prior
+//                energy sum_i alpha_i rho(K_i u) over the pixels its tile
+//                owns and of the data energy D(u, v) / lambda (eq. 2.5, 2.6);
+//                the gradient store is skipped when ub is NULL.
+constexpr int kStep = 0, kGrad = 1, kGradEnergy = 2;
 
 template <int M>
 struct Geo {
@@ -126,28 +137,32 @@ struct Ring {
 // and the policy's operand tables (if it keeps any in LDS).
 constexpr int kLdsFloats = 160 * 1024 / 4;
 
-template <int M, typename Math>
+// The energy mode adds the weights alpha_i (64 floats) after the tables.
+constexpr int kAlphaFloats = 64;
+
+template <int M, typename Math, int MODE = kStep>
 constexpr size_t lds_fixed_floats()
 {
     using G = Geo<M>;
     return (size_t)Math::kNW * Math::kScratchFloats +
-           (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * Math::kHS + Math::kTabFloats;
+           (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * Math::kHS + Math::kTabFloats +
+           (MODE == kGradEnergy ? kAlphaFloats : 0);
 }
 
-template <int M, typename Math>
+template <int M, typename Math, int MODE = kStep>
 size_t lds_bytes(int ty_max)
 {
     using G = Geo<M>;
     return sizeof(float) * ((size_t)(ty_max + 4 * G::R + G::UROWS_EXTRA) * Math::kUS +
-                            lds_fixed_floats<M, Math>());
+                            lds_fixed_floats<M, Math, MODE>());
 }
 
 // Tallest tile whose workgroup fits the LDS.
-template <int M, typename Math>
+template <int M, typename Math, int MODE = kStep>
 constexpr int rows_limit()
 {
     using G = Geo<M>;
-    const long rows = ((long)kLdsFloats - (long)lds_fixed_floats<M, Math>()) / Math::kUS -
+    const long rows = ((long)kLdsFloats - (long)lds_fixed_floats<M, Math, MODE>()) / Math::kUS -
                       (4 * G::R + G::UROWS_EXTRA);
     return rows < kMaxTileRows ? (int)rows : kMaxTileRows;
 }
@@ -328,9 +343,12 @@ struct MathF32 {
     }
 
     // Influence, adjoint, tap contributions C[px][tap] into the scratch.
-    template <bool MASK>
+    // EN: also adds alpha_f rho(z_f) of the lane's filters (alpha from the
+    // LDS table `al`) to `en` when the pixel is one the tile owns.
+    template <bool MASK, bool EN = false>
     __device__ __forceinline__ void adjoint(const Acc &a, bool inside, int p, int g,
-                                            float *Sw) const
+                                            float *Sw, bool own = false, float *en = nullptr,
+                                            const float *al = nullptr) const
     {
         f32x4 c[G::NTB];
 #pragma unroll
@@ -340,9 +358,12 @@ struct MathF32 {
         for (int fb = 0; fb < NFB; ++fb) {
             Ops o;
             fetch(fb, o);
+            f32x4 al4 = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (EN) al4 = *(const lquad *)(al + 16 * fb + 4 * g);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float zz = fmaf(last_f(o, fb, j), a.ul, a.z[fb][j]);
+                if constexpr (EN) *en += own ? al4[j] * student_t_rho(zz) : 0.0f;
                 float phi = zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f));
                 if (MASK) phi = inside ? phi : 0.0f;
 #pragma unroll
@@ -380,10 +401,12 @@ struct MathF32 {
 //   t0 forward A   [KS][NFB][64][8]  A[filter 16fb + l%16][tap 32s + 8(l/16) + e]
 //   t1 adjoint B   [KG][64][8]       B[slot 4s + l/16 = (b, j), filter 8j + e][a = l%16]
 //                                    = 2 alpha_f k_f(a, b), slot = j * M + b
-template <int M, int NFB, typename P>
+// NWV: waves per workgroup (12 for the step; the energy mode, whose
+// log(1 + z^2) terms need more registers, runs 8).
+template <int M, int NFB, typename P, int NWV = kWavesP16>
 struct MathP16 {
     using G = Geo<M>;
-    static constexpr int kNW = kWavesP16;
+    static constexpr int kNW = NWV;
     static constexpr bool kTwo = true;
     static constexpr bool kGather = true;
     static constexpr int kTabFloats = 0;
@@ -501,16 +524,24 @@ struct MathP16 {
     // Influence of block k (FP32), rounded to P, into the psi scratch:
     // filters 16fb + 4g .. + 3 of q-position 16k + p (8 bytes per fb); a
     // q-position outside the image (inside = false) stores zeros.
+    // EN: also adds alpha_f rho(z_f) of the lane's filters to `en` when the
+    // pixel is one the tile owns (as MathF32::adjoint).
+    template <bool EN = false>
     __device__ __forceinline__ void store_psi(const Acc &a, bool inside, int p, int g,
-                                              unsigned short *Pw, int k) const
+                                              unsigned short *Pw, int k, bool own = false,
+                                              float *en = nullptr,
+                                              const float *al = nullptr) const
     {
         unsigned short *row = Pw + (16 * k + p + G::R) * PS + 4 * g;
 #pragma unroll
         for (int fb = 0; fb < NFB; ++fb) {
             vec4 v;
+            f32x4 al4 = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (EN) al4 = *(const lquad *)(al + 16 * fb + 4 * g);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float zz = a.z[fb][i];
+                if constexpr (EN) *en += own ? al4[i] * student_t_rho(zz) : 0.0f;
                 v[i] = (P)(zz * __builtin_amdgcn_rcpf(fmaf(zz, zz, 1.0f)));
             }
             u32x2 w = __builtin_bit_cast(u32x2, v);
@@ -550,14 +581,16 @@ struct MathP16 {
     }
 };
 
-template <int M, typename Math>
+template <int M, typename Math, int MODE = kStep>
 __global__ __launch_bounds__(64 * Math::kNW)
 __attribute__((amdgpu_waves_per_eu(Math::kNW / 4, Math::kNW / 4)))
 void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                        const void *__restrict__ t0, const void *__restrict__ t1,
                        const void *__restrict__ t2, const void *__restrict__ t3,
-                       int iter, int ty_max, int tile0)
+                       int iter, int ty_max, int tile0, const float *__restrict__ alpha,
+                       float *__restrict__ epart)
 {
+    constexpr bool GRAD = MODE != kStep, EN = MODE == kGradEnergy;
     using G = Geo<M>;
     constexpr int R = G::R;
     constexpr int NW = Math::kNW;
@@ -593,6 +626,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *S = U + (size_t)(ty_max + 4 * R + G::UROWS_EXTRA) * Math::kUS;  // per-wave scratch
     float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
     float *Tab = Hr + (size_t)HR * M * Math::kHS;          // the policy's tables
+    float *Al = Tab + Math::kTabFloats;                    // alpha_i (energy mode)
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
     unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
 
@@ -671,6 +705,10 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
     Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
+    if constexpr (EN)
+        if (threadIdx.x < kAlphaFloats) Al[threadIdx.x] = alpha[threadIdx.x];
+    // per-lane partial energies of the pixels this tile owns (energy mode)
+    float e_prior = 0.0f, e_data = 0.0f;
     // Every global load of the prologue (operand tables, u tile) has landed:
     // said explicitly, so that the compiler's wait counting does not carry
     // them into the step loop, where a conservative wait would also wait
@@ -689,17 +727,21 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // ---- influence, adjoint bank, tap contributions into the scratch ------
     // Pixels of block k outside the image carry psi = 0 (the adjoint's
     // input vanishes off the image); blocks wholly inside skip the mask.
-    auto adjoint = [&](int k, const Acc &acc) {
+    // Energy mode: a q-row pixel counts towards the energy only in the tile
+    // that owns it (rows y0..y1-1, columns x0..x1-1), so that each image
+    // pixel is counted once over the tiles.
+    auto adjoint = [&](int k, const Acc &acc, bool own_row) {
         const int q0 = x0 - R + 16 * k;
+        const int qx = q0 + p;
+        const bool own = own_row && qx >= x0 && qx < x1;
         if constexpr (Math::kGather) {
-            const int qx = q0 + p;
-            mth.store_psi(acc, qx >= 0 && qx < W, p, g, Pw, k);
+            mth.template store_psi<EN>(acc, qx >= 0 && qx < W, p, g, Pw, k, own, &e_prior, Al);
         } else {
             if (q0 >= 0 && q0 + 15 < W) {
-                mth.template adjoint<false>(acc, true, p, g, Sw);
+                mth.template adjoint<false, EN>(acc, true, p, g, Sw, own, &e_prior, Al);
             } else {
-                const int qx = q0 + p;
-                mth.template adjoint<true>(acc, qx >= 0 && qx < W, p, g, Sw);
+                mth.template adjoint<true, EN>(acc, qx >= 0 && qx < W, p, g, Sw, own, &e_prior,
+                                               Al);
             }
         }
     };
@@ -738,7 +780,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         const int orow = st * NW - 2 * R + wave;
         if (orow >= 0 && orow < ty && lane < tx) {
             const long pix = (long)(y0 + orow) * W + x0 + lane;
-            pf_up = uprev[pix];
+            if constexpr (!GRAD) pf_up = uprev[pix];
             pf_y = counts[pix];
             if constexpr (Math::kPairTile) pf_u = ucur[pix];   // the tile holds P pairs
         }
@@ -797,17 +839,25 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         float uc;
         if constexpr (Math::kPairTile) uc = pf_u;
         else uc = U[(orow + 2 * R) * Math::kUS + lane + 2 * R];
-        const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
         // the column laundered: its 64-bit address is formed here each step
         // rather than hoisted out of the step loop into a register pair
         int xs = x;
         asm volatile("" : "+v"(xs));
-        uprev[(long)y * W + xs] = prox_fast(ut, anscombe_fast(pf_y), J.tl, J.q1, J.data_term);
+        if constexpr (GRAD) {
+            const float v = anscombe(pf_y);
+            if constexpr (EN) e_data += data_energy(uc, v, J.data_term);
+            if (uprev)
+                uprev[(long)y * W + xs] = gsum + J.lambda * data_gradient(uc, v, J.data_term);
+        } else {
+            const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
+            uprev[(long)y * W + xs] = prox_fast(ut, anscombe_fast(pf_y), J.tl, J.q1, J.data_term);
+        }
     };
 
     auto qrow = [&](int st) {
         const int qr = st * NW + wave;
         const int qy = y0 - R + qr;
+        const bool own_row = qr >= R && qr < R + ty;
         if (qr < nq && qy >= 0 && qy < H) {
             float *Hs = Hr + (size_t)(qr % HR) * M * Math::kHS;
             Acc acc;
@@ -816,25 +866,26 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 // of blocks k - 1 .. k + 1, so it follows psi of block k + 1.
                 // Branch-free, two accumulators: the forward products of
                 // block k + 1 are issued before the influence of block k.
-                // (one accumulator where two would not fit the registers)
-                constexpr bool two = Math::kTwoAcc;
+                // (one accumulator where two would not fit the registers,
+                // and in the energy mode)
+                constexpr bool two = Math::kTwoAcc && !EN;
                 Acc acc1;
                 Acc &accb = two ? acc1 : acc;
                 forward(qr, 0, acc);
                 if (two) forward(qr, 1, accb);
-                adjoint(0, acc);
+                adjoint(0, acc, own_row);
                 if (!two) forward(qr, 1, accb);
                 if (two) forward(qr, 2, acc);
-                adjoint(1, accb);
+                adjoint(1, accb, own_row);
                 lds_order();
                 mth.gather(Pw, Hs, 0, p, g);
                 if (!two) forward(qr, 2, acc);
                 if (two) forward(qr, 3, accb);
-                adjoint(2, acc);
+                adjoint(2, acc, own_row);
                 lds_order();
                 mth.gather(Pw, Hs, 1, p, g);
                 if (!two) forward(qr, 3, accb);
-                adjoint(3, accb);
+                adjoint(3, accb, own_row);
                 lds_order();
                 mth.gather(Pw, Hs, 2, p, g);
                 mth.gather(Pw, Hs, 3, p, g);
@@ -843,14 +894,14 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 // software pipeline: the collapse of block k - 1 (LDS, VALU)
                 // is issued next to the forward MFMAs of block k
                 forward(qr, 0, acc);
-                adjoint(0, acc);
+                adjoint(0, acc, own_row);
 #pragma unroll
                 for (int k = 1; k < kQB; ++k) {
                     lds_order();
                     forward(qr, k, acc);
                     collapse(Hs, k - 1);
                     lds_order();
-                    adjoint(k, acc);
+                    adjoint(k, acc, own_row);
                 }
                 lds_order();
                 collapse(Hs, kQB - 1);
@@ -887,6 +938,30 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             lds_barrier();
         }
     }
+    if constexpr (EN) {
+        // The workgroup's partial energies: lanes, then waves, in a fixed
+        // order (the loop's last barrier has retired every LDS read, so the
+        // u tile's first floats are free).
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e_prior += __shfl_xor(e_prior, o);
+            e_data += __shfl_xor(e_data, o);
+        }
+        if (lane == 0) {
+            U[2 * wave] = e_prior;
+            U[2 * wave + 1] = e_data;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float sp = 0.0f, sd = 0.0f;
+            for (int w = 0; w < NW; ++w) {
+                sp += U[2 * w];
+                sd += U[2 * w + 1];
+            }
+            epart[2 * (long)bid] = sp;
+            epart[2 * (long)bid + 1] = sd;
+        }
+    }
 }
 
 // Job table upload through kernel arguments (no host-to-device copy, so the
@@ -906,13 +981,14 @@ __global__ void write_jobs_kernel(JobChunk c, JobDesc *dst)
 
 int nfb_for(int nf) { return (nf + 15) / 16; }
 
-template <int M, typename Math>
+template <int M, typename Math, int MODE = kStep>
 hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, int nblocks,
-                       int tile0, int iter, int ty_max, hipStream_t s)
+                       int tile0, int iter, int ty_max, hipStream_t s,
+                       const float *alpha = nullptr, float *epart = nullptr)
 {
     constexpr int NW = Math::kNW;
-    if (ty_max > rows_limit<M, Math>()) return hipErrorInvalidValue;
-    const size_t bytes = lds_bytes<M, Math>(ty_max);
+    if (ty_max > rows_limit<M, Math, MODE>()) return hipErrorInvalidValue;
+    const size_t bytes = lds_bytes<M, Math, MODE>(ty_max);
     // the dynamic-LDS limit is raised once per device (any thread)
     static std::atomic<uint64_t> attr_set{0};
     int dev = 0;
@@ -920,16 +996,55 @@ hipError_t launch_step(const void *const *tabs, const JobDesc *jobs, int njobs, 
     if (e != hipSuccess) return e;
     const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
     if (!bit || !(attr_set.load(std::memory_order_acquire) & bit)) {
-        e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math>,
+        e = hipFuncSetAttribute((const void *)fused_step_kernel<M, Math, MODE>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds_bytes<M, Math>(rows_limit<M, Math>()));
+                                (int)lds_bytes<M, Math, MODE>(rows_limit<M, Math, MODE>()));
         if (e != hipSuccess) return e;
         attr_set.fetch_or(bit, std::memory_order_release);
     }
-    fused_step_kernel<M, Math><<<nblocks, 64 * NW, bytes, s>>>(jobs, njobs, tabs[0], tabs[1],
-                                                                tabs[2], tabs[3], iter, ty_max,
-                                                                tile0);
+    fused_step_kernel<M, Math, MODE><<<nblocks, 64 * NW, bytes, s>>>(
+        jobs, njobs, tabs[0], tabs[1], tabs[2], tabs[3], iter, ty_max, tile0, alpha, epart);
     return hipGetLastError();
+}
+
+// Gradient modes: FP32 runs the 8-wave variant (built for every bank),
+// BF16 / FP16 their 12-wave variant.
+constexpr int kWavesP16Energy = 8;
+template <int MODE>
+constexpr int p16_waves() { return MODE == kGradEnergy ? kWavesP16Energy : kWavesP16; }
+
+template <int M, int NFB, int MODE>
+hipError_t launch_grad_prec(int prec, const FusedBank &b, const JobDesc *jobs, int njobs,
+                            int nblocks, int tile0, int ty_max, float *epart, hipStream_t s)
+{
+    constexpr int NWV = p16_waves<MODE>();
+    if (prec == FE_PREC_BF16) {
+        const void *t[4] = {b.bf_fwd, b.bf_adj, nullptr, nullptr};
+        return launch_step<M, MathP16<M, NFB, __bf16, NWV>, MODE>(t, jobs, njobs, nblocks, tile0, 0,
+                                                                   ty_max, s, b.alpha, epart);
+    }
+    if (prec == FE_PREC_FP16) {
+        const void *t[4] = {b.h_fwd, b.h_adj, nullptr, nullptr};
+        return launch_step<M, MathP16<M, NFB, _Float16, NWV>, MODE>(t, jobs, njobs, nblocks, tile0,
+                                                                     0, ty_max, s, b.alpha, epart);
+    }
+    const void *t[4] = {b.fwd, b.adj, b.lastf, b.lasta};
+    return launch_step<M, MathF32<M, NFB, false>, MODE>(t, jobs, njobs, nblocks, tile0, 0,
+                                                         ty_max, s, b.alpha, epart);
+}
+
+template <int M, int NFB>
+int rows_grad_prec(int prec, bool energy)
+{
+    constexpr int NWE = p16_waves<kGradEnergy>();
+    if (prec == FE_PREC_BF16)
+        return energy ? rows_limit<M, MathP16<M, NFB, __bf16, NWE>, kGradEnergy>()
+                      : rows_limit<M, MathP16<M, NFB, __bf16>, kGrad>();
+    if (prec == FE_PREC_FP16)
+        return energy ? rows_limit<M, MathP16<M, NFB, _Float16, NWE>, kGradEnergy>()
+                      : rows_limit<M, MathP16<M, NFB, _Float16>, kGrad>();
+    return energy ? rows_limit<M, MathF32<M, NFB, false>, kGradEnergy>()
+                  : rows_limit<M, MathF32<M, NFB, false>, kGrad>();
 }
 
 // The 12-wave FP32 variant is built where its registers fit three waves
@@ -971,6 +1086,54 @@ int rows_prec(int prec, int nw)
         return 0;
     }
     return nw == kWavesF32 ? rows_limit<M, MathF32<M, NFB, false>>() : 0;
+}
+
+hipError_t launch_grad_any(int prec, bool energy, const FusedBank &b, const JobDesc *jobs,
+                           int njobs, int nblocks, int tile0, int ty_max, float *epart,
+                           hipStream_t s)
+{
+#define FE_GRAD(MM, NB)                                                                       \
+    return energy ? launch_grad_prec<MM, NB, kGradEnergy>(prec, b, jobs, njobs, nblocks, tile0, \
+                                                          ty_max, epart, s)                   \
+                  : launch_grad_prec<MM, NB, kGrad>(prec, b, jobs, njobs, nblocks, tile0,     \
+                                                    ty_max, nullptr, s)
+    switch (b.m * 10 + b.nfb) {
+    case 31: FE_GRAD(3, 1);
+    case 32: FE_GRAD(3, 2);
+    case 33: FE_GRAD(3, 3);
+    case 34: FE_GRAD(3, 4);
+    case 51: FE_GRAD(5, 1);
+    case 52: FE_GRAD(5, 2);
+    case 53: FE_GRAD(5, 3);
+    case 54: FE_GRAD(5, 4);
+    case 71: FE_GRAD(7, 1);
+    case 72: FE_GRAD(7, 2);
+    case 73: FE_GRAD(7, 3);
+    case 74: FE_GRAD(7, 4);
+    default: return hipErrorInvalidValue;
+    }
+#undef FE_GRAD
+}
+
+int rows_grad_any(int m, int nfb, int prec, bool energy)
+{
+#define FE_ROWS(MM, NB) return rows_grad_prec<MM, NB>(prec, energy)
+    switch (m * 10 + nfb) {
+    case 31: FE_ROWS(3, 1);
+    case 32: FE_ROWS(3, 2);
+    case 33: FE_ROWS(3, 3);
+    case 34: FE_ROWS(3, 4);
+    case 51: FE_ROWS(5, 1);
+    case 52: FE_ROWS(5, 2);
+    case 53: FE_ROWS(5, 3);
+    case 54: FE_ROWS(5, 4);
+    case 71: FE_ROWS(7, 1);
+    case 72: FE_ROWS(7, 2);
+    case 73: FE_ROWS(7, 3);
+    case 74: FE_ROWS(7, 4);
+    default: return 0;
+    }
+#undef FE_ROWS
 }
 
 hipError_t launch_any(int prec, int nw, const FusedBank &b, const JobDesc *jobs, int njobs,
@@ -1083,6 +1246,13 @@ hipError_t fused_upload(const float *taps, const float *alpha, int m, int nf, Fu
         if (e == hipSuccess) e = hipMemcpy(*d, h.data(), h.size() * 2, hipMemcpyHostToDevice);
         return e;
     };
+    // the weights alpha_i, zero-padded to 64 (energy mode)
+    std::vector<float> al(kAlphaFloats, 0.0f);
+    for (int f = 0; f < nf && f < kAlphaFloats; ++f) al[f] = alpha[f];
+    hipError_t ea = hipMalloc((void **)&out->alpha, al.size() * sizeof(float));
+    if (ea == hipSuccess)
+        ea = hipMemcpy(out->alpha, al.data(), al.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (ea != hipSuccess) return ea;
     hipError_t e16 = up16(bff, &out->bf_fwd);
     if (e16 == hipSuccess) e16 = up16(bfa, &out->bf_adj);
     if (e16 == hipSuccess) e16 = up16(hf, &out->h_fwd);
@@ -1111,6 +1281,8 @@ void fused_release(FusedBank *b)
     (void)hipFree(b->bf_adj);
     (void)hipFree(b->h_fwd);
     (void)hipFree(b->h_adj);
+    (void)hipFree(b->alpha);
+    b->alpha = nullptr;
     b->fwd = b->adj = b->lastf = b->lasta = nullptr;
     b->bf_fwd = b->bf_adj = b->h_fwd = b->h_adj = nullptr;
 }
@@ -1324,6 +1496,135 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
             }
     }
     return hipSuccess;
+}
+
+// ---- gradient and energy (eq. 3.2, 2.5) ------------------------------------
+// One launch of the fused kernel in a gradient mode over every tile of every
+// image of a batch.  Workspace: [job table][2 floats per tile][one double
+// per image].
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+long grad_tiles_max(const FusedBank &bank, const GradItem *items, int n)
+{
+    const int R = (bank.m - 1) / 2, TX = kQW - 2 * R;
+    long t = 0;
+    for (int i = 0; i < n; ++i)
+        t += (long)((items[i].width + TX - 1) / TX) *
+             ((items[i].height + kMinTileRows - 1) / kMinTileRows);
+    return t;
+}
+size_t grad_part_offset(int n) { return al256(fused_table_bytes(n)); }
+size_t grad_energy_offset(const FusedBank &bank, const GradItem *items, int n)
+{
+    return grad_part_offset(n) + al256(2 * sizeof(float) * (size_t)grad_tiles_max(bank, items, n));
+}
+
+// Energy of each image of a gradient-mode launch: block j sums image j's
+// workgroup partials, E_j = sum of prior partials + lambda_j * sum of data
+// partials, in FP64, every thread over a fixed stride of the image's tiles,
+// then a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void energy_finish_kernel(const JobDesc *__restrict__ jobs,
+                                                            const float *__restrict__ epart,
+                                                            double *__restrict__ out)
+{
+    __shared__ double sp[256], sd[256];
+    const JobDesc J = jobs[blockIdx.x];
+    const long t0 = J.tile_base, nt = (long)J.ntx * J.nty;
+    double a = 0.0, b = 0.0;
+    for (long t = threadIdx.x; t < nt; t += 256) {
+        a += (double)epart[2 * (t0 + t)];
+        b += (double)epart[2 * (t0 + t) + 1];
+    }
+    sp[threadIdx.x] = a;
+    sd[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sp[threadIdx.x] += sp[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sp[0] + (double)J.lambda * sd[0];
+}
+}  // namespace
+
+size_t grad_workspace_bytes(const FusedBank &bank, const GradItem *items, int n)
+{
+    return grad_energy_offset(bank, items, n) + al256(sizeof(double) * (size_t)std::max(n, 1));
+}
+
+hipError_t run_grad(const FusedBank &bank, const GradItem *items, int n, int prec, bool energy,
+                    void *ws, double **energy_dev, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int m = bank.m, R = (m - 1) / 2, TX = kQW - 2 * R;
+    const int nw = prec == FE_PREC_FP32 ? kWavesF32
+                   : energy               ? kWavesP16Energy
+                                          : kWavesP16;
+    // tile height: the cost model's choice within the mode's LDS limit
+    std::vector<fe_job> jj(n);
+    std::vector<AdvanceItem> adv(n);
+    for (int i = 0; i < n; ++i) {
+        jj[i] = fe_job{};
+        jj[i].height = items[i].height;
+        jj[i].width = items[i].width;
+        jj[i].precision = prec;
+        adv[i] = AdvanceItem{&jj[i], nullptr, 0, 1};
+    }
+    const int hi = std::max(kMinTileRows, rows_grad_any(m, bank.nfb, prec, energy));
+    int ty = kMinTileRows;
+    double best = 1e300;
+    for (int t = kMinTileRows; t <= hi; ++t) {
+        const double c = plan_cost(m, adv.data(), n, nw, t);
+        if (c < best - 1e-9) {
+            best = c;
+            ty = t;
+        }
+    }
+    char *w = (char *)ws;
+    JobDesc *table = (JobDesc *)w;
+    float *epart = (float *)(w + grad_part_offset(n));
+    double *edev = (double *)(w + grad_energy_offset(bank, items, n));
+    long base = 0;
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+        JobChunk jc{};
+        jc.first = c0;
+        jc.count = std::min(kChunk, n - c0);
+        for (int i = 0; i < jc.count; ++i) {
+            const GradItem &it = items[c0 + i];
+            JobDesc &d = jc.d[i];
+            d.counts = it.counts;
+            d.ua = const_cast<float *>(it.u);   // read only: the gradient modes write ub
+            d.ub = it.grad;
+            d.H = it.height;
+            d.W = it.width;
+            d.ntx = (it.width + TX - 1) / TX;
+            d.nty = (it.height + ty - 1) / ty;
+            d.tile_base = (int)base;
+            base += (long)d.ntx * d.nty;
+            d.iters = 1;
+            d.it0 = 0;
+            d.lambda = it.lambda;
+            d.data_term = it.data_term;
+            if (base > INT_MAX) return hipErrorInvalidValue;   // tile indices are ints
+        }
+        write_jobs_kernel<<<1, kChunk, 0, s>>>(jc, table);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (base > grad_tiles_max(bank, items, n)) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    for (long t0 = 0; t0 < base && e == hipSuccess; t0 += kMaxLaunchTiles) {
+        const int nb = (int)std::min<long>(kMaxLaunchTiles, base - t0);
+        e = launch_grad_any(prec, energy, bank, table, n, nb, (int)t0, ty, epart, s);
+    }
+    if (e == hipSuccess && energy) {
+        energy_finish_kernel<<<n, 256, 0, s>>>(table, epart, edev);
+        e = hipGetLastError();
+    }
+    if (energy_dev) *energy_dev = edev;
+    return e;
 }
 
 }  // namespace fe

@@ -23,7 +23,8 @@ from . import FeError, JobSpec, _Job, library, make_jobs
 
 class _Cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("iters_per_tick", ctypes.c_int32),
-                ("max_active", ctypes.c_int32), ("ticks_in_flight", ctypes.c_int32)]
+                ("max_active", ctypes.c_int32), ("ticks_in_flight", ctypes.c_int32),
+                ("tick_pixel_iters", ctypes.c_int64)]
 
 
 class _Completion(ctypes.Structure):
@@ -64,11 +65,11 @@ class Server:
     """fe_server_create / submit / poll / destroy."""
 
     def __init__(self, prior, budget_bytes, iters_per_tick=20, max_active=4096,
-                 ticks_in_flight=2):
+                 ticks_in_flight=2, tick_pixel_iters=0):
         lib = _bind()
         self.prior = prior
         cfg = _Cfg(int(budget_bytes), int(iters_per_tick), int(max_active),
-                   int(ticks_in_flight))
+                   int(ticks_in_flight), int(tick_pixel_iters))
         h = ctypes.c_void_p()
         _scheck(lib.fe_server_create(prior.handle, ctypes.byref(cfg), None, ctypes.byref(h)))
         self._h = h
@@ -225,13 +226,22 @@ def mean_psnr(outs, crops, pool_side=2048, n_clean=4, seed=77):
     return float(np.mean(psnrs))
 
 
+# Work per tick of the batched form (pixel-iterations): 8 Mpx x 25
+# iterations, a few milliseconds of device time, enough tiles to fill the
+# chip; see serve().
+TICK_WORK = 8 * (1 << 20) * 25
+
+
 def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25, crops=None,
-          progress_s=None):
-    """One serving run; batched: continuous batching, else one job at a time."""
+          progress_s=None, tick_work=TICK_WORK):
+    """One serving run; batched: continuous batching (oldest jobs first,
+    tick_work pixel-iterations per tick, 0: every resident job every tick),
+    else one job at a time."""
     import torch
     srv = Server(prior, int(budget_gb * (1 << 30)),
                  iters_per_tick=iters_per_tick if batched else 1 << 20,
-                 max_active=4096 if batched else 1, ticks_in_flight=2)
+                 max_active=4096 if batched else 1, ticks_in_flight=2,
+                 tick_pixel_iters=tick_work if batched else 0)
     try:
         comps, outs, wall = run_stream(srv, times, specs, timeout_s=1200.0,
                                        progress_s=progress_s)
@@ -245,31 +255,41 @@ def serve(prior, times, specs, pxit, batched, budget_gb=64.0, iters_per_tick=25,
 
 
 def serving_report(prior, n_requests, loads=(0.9,), precision="bf16", max_side=2048,
-                   log=None, forms=("batched", "single"), progress_s=None):
+                   log=None, forms=("batched", "single"), progress_s=None,
+                   tick_work=TICK_WORK, same_rate_loads=()):
     """Both serving forms on the same request stream: saturation (every
     request at t = 0) and each offered load as a fraction of the form's own
     saturation rate; mean PSNR at saturation for the equal-quality check.
-    `log` receives one JSON line per finished run."""
-    res = {"requests": n_requests, "contraction_precision": precision}
+    same_rate_loads: the batched form also runs at these fractions of the
+    one-image-at-a-time form's saturation rate (equal absolute arrival
+    rates).  `log` receives one JSON line per finished run."""
+    res = {"requests": n_requests, "contraction_precision": precision,
+           "tick_pixel_iters": tick_work}
     runs = {"batched": ("batched_" + precision, True, precision),
             "single": ("single_fp32", False, "fp32")}
-    for form in forms:
+    # the one-image form first when both run: its rate sets the same-rate rows
+    order = [f for f in ("single", "batched") if f in forms]
+    for form in order:
         mode, batched, prec = runs[form]
         _, specs, pxit, crops = build_requests(n_requests, 1e9, prec, hi=max_side)
         sat = serve(prior, np.zeros(len(specs)), specs, pxit, batched, crops=crops,
-                    progress_s=progress_s)
+                    progress_s=progress_s, tick_work=tick_work)
         del specs
         out = {"saturation": sat}
         if log:
             log(json.dumps({mode: {"saturation": sat}}))
-        for load in loads:
-            times, specs, pxit, _ = build_requests(n_requests, load * sat["images_per_s"], prec,
-                                                   hi=max_side)
-            out["load_%g" % load] = serve(prior, times, specs, pxit, batched,
-                                          progress_s=progress_s)
+        rows = [("load_%g" % ld, ld * sat["images_per_s"]) for ld in loads]
+        if batched and "single_fp32" in res:
+            rate1 = res["single_fp32"]["saturation"]["images_per_s"]
+            rows += [("single_rate_%g" % ld, ld * rate1) for ld in same_rate_loads]
+        for name, rate in rows:
+            times, specs, pxit, _ = build_requests(n_requests, rate, prec, hi=max_side)
+            out[name] = serve(prior, times, specs, pxit, batched, progress_s=progress_s,
+                              tick_work=tick_work)
+            out[name]["offered_per_s"] = round(rate, 2)
             del specs
             if log:
-                log(json.dumps({mode: {"load_%g" % load: out["load_%g" % load]}}))
+                log(json.dumps({mode: {name: out[name]}}))
         res[mode] = out
     if "batched_" + precision in res and "single_fp32" in res:
         b, f = res["batched_" + precision], res["single_fp32"]
@@ -292,12 +312,20 @@ def main(argv=None):
                     help="seconds between progress lines during a run (0: none)")
     ap.add_argument("--forms", default="batched,single",
                     help="batched (continuous batching), single (one FP32 image at a time)")
+    ap.add_argument("--tick-work", type=int, default=TICK_WORK,
+                    help="pixel-iterations per tick of the batched form, oldest jobs "
+                         "first (0: every resident job advances every tick)")
+    ap.add_argument("--same-rate-loads", default="",
+                    help="also run the batched form at these fractions of the "
+                         "one-image form's saturation rate")
     a = ap.parse_args(argv)
     k, al = prior_for(7, 48)
     prior = Prior(k, al)
+    same = [float(x) for x in a.same_rate_loads.split(",") if x]
     res = serving_report(prior, a.requests, [float(x) for x in a.loads.split(",")],
                          a.precision, a.max_side, log=lambda s: print(s, flush=True),
-                         forms=tuple(a.forms.split(",")), progress_s=a.progress)
+                         forms=tuple(a.forms.split(",")), progress_s=a.progress,
+                         tick_work=a.tick_work, same_rate_loads=same)
     print(json.dumps(res))
 
 

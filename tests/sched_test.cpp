@@ -90,11 +90,50 @@ static void order_and_caps()
           t.finishing[0] == z);
 }
 
+static void tick_budget()
+{
+    // work budget 1000 pixel-iterations per tick, 10 iterations per job
+    fe::Scheduler s(1 << 20, 10, 100, 1000);
+    const uint64_t big = s.submit(4096, 30, 0.0, 200);    // 2000 px-it per tick alone
+    const uint64_t a = s.submit(1024, 10, 0.1, 50);
+    const uint64_t b = s.submit(1024, 10, 0.2, 50);
+    fe::TickPlan t = s.plan(1.0);
+    // all admitted; the oldest (over budget on its own) advances, the rest wait
+    CHECK(t.admitted.size() == 3);
+    CHECK(t.active.size() == 3 && t.active[0] == big);
+    CHECK(t.count[0] == 10 && t.count[1] == 0 && t.count[2] == 0);
+    CHECK(t.finishing.empty());
+    t = s.plan(2.0);
+    CHECK(t.count[0] == 10 && t.count[1] == 0 && t.done_before[0] == 10);
+    t = s.plan(3.0);
+    CHECK(t.count[0] == 10 && t.finishing.size() == 1 && t.finishing[0] == big);
+    s.retire(t.finishing);
+    // the two small ones fit one budget together: both advance and finish
+    t = s.plan(4.0);
+    CHECK(t.active.size() == 2 && t.count[0] == 10 && t.count[1] == 10);
+    CHECK(t.finishing.size() == 2 && t.finishing[0] == a && t.finishing[1] == b);
+    s.retire(t.finishing);
+    CHECK(s.active() == 0 && s.arena().used() == 0);
+    // the budget is reached part-way: the jobs after the one that reaches it wait
+    fe::Scheduler s2(1 << 20, 4, 100, 1000);
+    for (int i = 0; i < 5; ++i) s2.submit(256, 8, 0.0, 100);   // 400 px-it per tick each
+    t = s2.plan(0.0);
+    CHECK(t.active.size() == 5);
+    CHECK(t.count[0] == 4 && t.count[1] == 4 && t.count[2] == 4);   // 1200 >= 1000
+    CHECK(t.count[3] == 0 && t.count[4] == 0);
+    // without a budget every resident job advances (processor sharing)
+    fe::Scheduler s3(1 << 20, 4, 100, 0);
+    for (int i = 0; i < 5; ++i) s3.submit(256, 8, 0.0, 100);
+    t = s3.plan(0.0);
+    for (size_t i = 0; i < t.count.size(); ++i) CHECK(t.count[i] == 4);
+}
+
 int main()
 {
     arena_tests();
     scheduler_tests();
     order_and_caps();
+    tick_budget();
     std::printf("OK\n");
     return 0;
 }
