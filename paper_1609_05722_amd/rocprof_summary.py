@@ -34,10 +34,15 @@ def code_hash(path):
 def short_name(name):
     """A kernel name without its namespaces and trailing parameter list, so
     that its template arguments fit a line."""
-    m = re.search(r"fused_step_kernelILi(\d)ENS0_7MathP16ILi(\d)ELi(\d)EDF16([b_])", name)
+    m = re.search(r"fused_step_kernelILi(\d)ENS0_7MathP16ILi(\d)ELi(\d)EDF16([b_])"
+                  r"(?:Li(\d+)EEELi(\d)E)?", name)
     if m:   # mangled (the demangler leaves the 16-bit float types alone)
+        p16 = "__bf16" if m.group(4) == "b" else "_Float16"
+        if m.group(5):   # waves per workgroup and mode (0 step, 1 gradient, 2 + energy)
+            return "fused_step_kernel<%s, MathP16<%s, %s, %s, %s>, %s>" % (
+                m.group(1), m.group(2), m.group(3), p16, m.group(5), m.group(6))
         return "fused_step_kernel<%s, MathP16<%s, %s, %s> >" % (
-            m.group(1), m.group(2), m.group(3), "__bf16" if m.group(4) == "b" else "_Float16")
+            m.group(1), m.group(2), m.group(3), p16)
     for ns in ("fe::(anonymous namespace)::", "fe::"):
         name = name.replace(ns, "")
     if name.startswith("void "):
@@ -46,18 +51,24 @@ def short_name(name):
     return name[:cut + 1] if cut > 0 else name
 
 
-def kernel_stats(db, like=None):
+def kernel_stats(db, like=None, by_grid=False):
+    """Dispatch counts and durations per kernel, or per (kernel, grid) with
+    by_grid (one kernel launched on different workloads has one line per
+    launch shape; `grid` is the work-item count of the launch)."""
     con = sqlite3.connect(db)
-    q = ("select name, count(*), avg(duration), min(duration), max(duration), "
-         "sum(duration) from kernels group by name order by sum(duration) desc")
+    grid = "grid_x * grid_y * grid_z" if by_grid else "0"
+    group = "name, grid_x * grid_y * grid_z" if by_grid else "name"
+    q = ("select name, %s, count(*), avg(duration), min(duration), max(duration), "
+         "sum(duration) from kernels group by %s order by sum(duration) desc" % (grid, group))
     rows = list(con.execute(q))
-    total = sum(r[5] for r in rows) or 1
+    total = sum(r[6] for r in rows) or 1
     out = []
-    for name, n, avg, mn, mx, tot in rows:
+    for name, grid, n, avg, mn, mx, tot in rows:
         if like and like not in name:
             continue
-        out.append({"kernel": name, "calls": n, "avg_us": avg / 1e3, "min_us": mn / 1e3,
-                    "max_us": mx / 1e3, "total_ms": tot / 1e6, "pct": 100.0 * tot / total})
+        out.append({"kernel": name, "grid": grid, "calls": n, "avg_us": avg / 1e3,
+                    "min_us": mn / 1e3, "max_us": mx / 1e3, "total_ms": tot / 1e6,
+                    "pct": 100.0 * tot / total})
     return out
 
 
@@ -119,6 +130,8 @@ def main(argv=None):
     s1 = sub.add_parser("stats")
     s1.add_argument("db")
     s1.add_argument("--kernel")
+    s1.add_argument("--by-grid", action="store_true",
+                    help="one line per kernel and launch shape (work-items)")
     s2 = sub.add_parser("pmc")
     s2.add_argument("db")
     s2.add_argument("--kernel")
@@ -133,9 +146,10 @@ def main(argv=None):
     s3.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        for r in kernel_stats(a.db, a.kernel):
-            print("%-90s calls=%-6d avg=%9.2f us min=%9.2f max=%9.2f total=%9.3f ms %5.1f%%"
-                  % (short_name(r["kernel"])[:90], r["calls"], r["avg_us"], r["min_us"],
+        for r in kernel_stats(a.db, a.kernel, a.by_grid):
+            grid = " grid=%-9d" % r["grid"] if a.by_grid else ""
+            print("%-70s%s calls=%-6d avg=%9.2f us min=%9.2f max=%9.2f total=%9.3f ms %5.1f%%"
+                  % (short_name(r["kernel"])[:70], grid, r["calls"], r["avg_us"], r["min_us"],
                      r["max_us"], r["total_ms"], r["pct"]))
     elif a.cmd == "pmc":
         for k, v in pmc_means(a.db, a.kernel).items():

@@ -27,6 +27,10 @@ def test_short_name():
                "7JobDescE")
     assert rs.short_name(mangled) == "fused_step_kernel<7, MathP16<7, 3, __bf16> >"
     assert rs.short_name(mangled.replace("DF16b", "DF16_")).endswith("_Float16> >")
+    # with the waves-per-workgroup and mode template arguments
+    mangled2 = ("_ZN2fe12_GLOBAL__N_117fused_step_kernelILi7ENS0_7MathP16ILi7ELi3EDF16bLi8EEELi2EEEv"
+                "PKNS0_7JobDescE")
+    assert rs.short_name(mangled2) == "fused_step_kernel<7, MathP16<7, 3, __bf16, 8>, 2>"
 
 
 def test_code_hash_ignores_comments_only(tmp_path):
@@ -69,6 +73,25 @@ def test_traffic_scales_by_the_copy(tmp_path):
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     assert rec["bytes_per_launch"] == pytest.approx(1001.0 * 1024 * 2 + 500.0 * 1024)
     assert rec["kernel_code_sha256_16"] == rs.code_hash(str(src))
+
+
+def test_kernel_stats_by_launch_shape(tmp_path):
+    """One kernel launched on two workloads: one line per launch shape with
+    --by-grid, one merged line without."""
+    db = str(tmp_path / "k.db")
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration real, grid_x int, grid_y int, "
+                "grid_z int)")
+    for d, g in ((100e3, 129024), (120e3, 129024), (30e3, 116736)):
+        con.execute("insert into kernels values (?, ?, ?, 1, 1)", ("fused_step_kernel", d, g))
+    con.commit()
+    con.close()
+    merged = rs.kernel_stats(db)
+    assert len(merged) == 1 and merged[0]["calls"] == 3
+    assert merged[0]["avg_us"] == pytest.approx(250.0 / 3)
+    split = {r["grid"]: r for r in rs.kernel_stats(db, by_grid=True)}
+    assert split[129024]["calls"] == 2 and split[129024]["avg_us"] == pytest.approx(110.0)
+    assert split[116736]["avg_us"] == pytest.approx(30.0)
 
 
 def test_accuracy_block():
