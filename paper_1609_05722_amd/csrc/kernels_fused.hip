@@ -844,10 +844,10 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         int xs = x;
         asm volatile("" : "+v"(xs));
         if constexpr (GRAD) {
-            const float v = anscombe(pf_y);
+            const float v = anscombe_fast(pf_y);
             if constexpr (EN) e_data += data_energy(uc, v, J.data_term);
             if (uprev)
-                uprev[(long)y * W + xs] = gsum + J.lambda * data_gradient(uc, v, J.data_term);
+                uprev[(long)y * W + xs] = gsum + J.lambda * data_gradient_fast(uc, v, J.data_term);
         } else {
             const float ut = inertial_step(uc, pf_up, gsum, J.tau, J.gamma);
             uprev[(long)y * W + xs] = prox_fast(ut, anscombe_fast(pf_y), J.tl, J.q1, J.data_term);
