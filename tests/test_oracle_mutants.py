@@ -74,6 +74,8 @@ MUTANTS = [
      "for (long p = 0; p < n; ++p) grad[p] += 0.0 * gd[p];", pins.grad_full_fd, 1e-3),
     ("idiv_energy_log", "t[p] = u[p] - v[p] * log(u[p]);", "t[p] = u[p] - log(u[p]);",
      pins.grad_full_fd, 1e-3),
+    ("idiv_energy_linear_term", "t[p] = u[p] - v[p] * log(u[p]);",
+     "t[p] = 0.5 * u[p] - v[p] * log(u[p]);", pins.idiv_energy_vs_kl, 1e-6),
     ("energy_log_argument", "log(1.0 + z * z)", "log(2.0 + z * z)",
      pins.energy_prior_vs_dense, 1e-3),
     ("quadratic_energy_half", "0.5 * d * d", "d * d",
