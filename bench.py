@@ -32,6 +32,17 @@ def flops_per_px_it(m, nf):
     return 4 * nf * m * m
 
 
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: one FP32 op per slot
+
+
+def valu_slots_per_px_it(nf):
+    """Algorithmic FP32 vector work of one pixel-iteration in lane issue
+    slots: the influence of every filter, z / (1 + z^2) (an FMA, a reciprocal
+    at a quarter of the full rate, so 4 slots, and a multiply), plus the
+    inertial step (3) and the prox (about 10 with its square root)."""
+    return nf * (1 + 4 + 1) + 3 + 10
+
+
 def hbm_bytes_per_px_it():
     """Algorithmic HBM bytes of one pixel-iteration in FP32: read u^n,
     u^{n-1} and the counts y, write u^{n+1}."""
@@ -525,6 +536,17 @@ def main():
                            "launch_us": round(launch_p * 1e3, 2),
                            "achieved_TFLOPs": round(ach, 3),
                            "frac_of_mfma_peak": round(ach / MFMA16_PEAK_TFLOPS, 4)}
+            # matrix and FP32 vector work one after the other (they overlap only
+            # in part on gfx950): the bound of the reduced-precision step
+            t_mfma = flops_per_px_it(m, nf) / (MFMA16_PEAK_TFLOPS * 1e12)
+            t_valu = valu_slots_per_px_it(nf) / VALU_LANE_SLOTS_PER_S
+            peak = 1.0 / (t_mfma + t_valu) / 1e9
+            got = px_per_launch / (launch_p * 1e-3) / 1e9
+            mixed[prec]["roofline_mfma_valu"] = {
+                "bound": "mfma+alu", "unit": "Gpixel-iter/s", "achieved": round(got, 2),
+                "peak": round(peak, 2), "frac": round(got / peak, 4),
+                "valu_slots_per_px_it": valu_slots_per_px_it(nf),
+                "mfma_flop_per_px_it": flops_per_px_it(m, nf)}
         return mixed
 
     def serving_section():
