@@ -84,6 +84,11 @@ def test_null_context_is_rejected(lib):
     assert lib.fe_workspace_size(None, None, 0, ctypes.byref(sz)) == fe.FE_ERR_INVALID
     assert lib.fe_denoise(None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_energy_grad_workspace_size(None, 8, 8, ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    assert lib.fe_energy_grad_batch_workspace_size(None, None, 0,
+                                                   ctypes.byref(sz)) == fe.FE_ERR_INVALID
+    assert lib.fe_energy_grad_batch(None, None, 0, 0, None, None, 0, None) == fe.FE_ERR_INVALID
+    assert lib.fe_energy_grad(None, 8, 8, None, None, 1.0, 1, 0, None, None, None, 0,
+                              None) == fe.FE_ERR_INVALID
     lib.fe_destroy(None)  # NULL-safe
 
 
@@ -95,6 +100,7 @@ def test_stepping_calls_validate_before_device_work(lib):
     assert lib.fe_begin(None, None, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_advance(None, None, None, None, None, 0, None, 0, None) == fe.FE_ERR_INVALID
     assert lib.fe_end(None, None, None, None, 0, None) == fe.FE_ERR_INVALID
+    assert lib.fe_advance_noalloc(None, None, None, None, None, 0, None) == fe.FE_ERR_INVALID
 
 
 def test_server_calls_validate_before_device_work(lib):

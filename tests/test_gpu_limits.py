@@ -183,3 +183,74 @@ def test_largest_images_sampled_pixels(fe, torch, bank, H, W, period, peak, data
         eu = abs(ug[n] - uo[ro, co]) / max(abs(uo[ro, co]), 1.0)
         ex = abs(xg[n] - xo[ro, co]) / max(abs(xo[ro, co]), 1.0)
         assert eu <= TOL and ex <= TOL, ((py, px), eu, ex)
+
+
+@pytest.mark.parametrize("H,W,period,peak,data_term", _MAX,
+                         ids=["%dx%d" % (m[0], m[1]) for m in _MAX])
+def test_largest_images_energy_and_gradient(fe, torch, bank, H, W, period, peak, data_term):
+    """fe_energy_grad at the largest sizes (several launches over the tiles).
+    (1) A constant image: every filter response vanishes (zero-mean filters,
+    symmetric extension), so E = lambda * N * D(c, v) with D of eq. 3.4 / 3.6
+    in closed form, which holds only if every pixel's data energy is counted
+    by exactly one tile; the gradient is lambda * grad D everywhere.
+    (2) A seeded image repeated with a period: the gradient at sampled pixels
+    against the oracle on crops reaching 2r + 1 beyond them (grad E at a pixel
+    depends on u within 2r), or to the true border."""
+    prior, k, a = bank
+    r = 3
+    lam = 30.0
+    print("energy/gradient case %dx%d (%.3f G px) dt=%d" % (H, W, H * W / 1e9, data_term),
+          flush=True)
+    # (1) constant counts and image
+    cval, uval = 3.0, 3.25
+    c = torch.full((H, W), cval, device="cuda")
+    u = torch.full((H, W), uval, device="cuda")
+    e, g = fe.energy_grad(c, u, prior, lam, data_term)
+    torch.cuda.synchronize()
+    v = 2.0 * np.sqrt(np.float64(np.float32(cval)) + 0.375)
+    uu = np.float64(np.float32(uval))
+    d = 0.5 * (uu - v) ** 2 if data_term == QUADRATIC else uu - v * np.log(uu)
+    dg = (uu - v) if data_term == QUADRATIC else (1.0 - v / uu)
+    e_ref = np.float64(np.float32(lam)) * H * W * d
+    # 1e-5: the device rounds v to FP32 (about 1e-6 relative in d for the
+    # quadratic term at u - v = -0.42); a tile counted twice or not at all
+    # moves E by a whole tile's share, a row of overlap by ~1 %
+    assert abs(e - e_ref) <= 1e-5 * abs(e_ref), (e, e_ref)
+    gs = g[::max(1, H // 7), ::max(1, W // 7)].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(gs - lam * dg)) <= 1e-4 * max(abs(lam * dg), 1e-3), \
+        np.max(np.abs(gs - lam * dg))
+    del g
+    # (2) the seeded tile repeated over the image
+    ph, pw = period
+    _, tile = noisy_pair(53, 54, ph, pw, peak)
+    tile = np.ascontiguousarray(tile, np.float32)
+    ut = (oracle.anscombe(tile) + np.random.default_rng(7).uniform(-0.3, 0.3, tile.shape)
+          ).astype(np.float32)
+    reps = ((H + ph - 1) // ph, (W + pw - 1) // pw)
+    c.copy_(torch.from_numpy(tile).cuda().repeat(*reps)[:H, :W])
+    u.copy_(torch.from_numpy(ut).cuda().repeat(*reps)[:H, :W])
+    _, g = fe.energy_grad(c, u, prior, lam, data_term, want_energy=False)
+    torch.cuda.synchronize()
+    del c, u
+    rng = np.random.default_rng(12)
+    pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, W // 2), (H - 1, W // 3),
+           (H // 3, W - 1), (min(1, H - 1), 1), (max(H - 2, 0), W - 3)]
+    pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(24)]
+    iy = torch.tensor([p[0] for p in pts], device="cuda")
+    ix = torch.tensor([p[1] for p in pts], device="cuda")
+    gg = g[iy, ix].cpu().numpy().astype(np.float64)
+    del g
+    torch.cuda.empty_cache()
+    marg = 2 * r + 1
+    for n, (py, px) in enumerate(pts):
+        y0, y1 = max(0, py - marg), min(H, py + marg + 1)
+        x0, x1 = max(0, px - marg), min(W, px + marg + 1)
+        rows, cols = np.arange(y0, y1) % ph, np.arange(x0, x1) % pw
+        cc, uc = tile[np.ix_(rows, cols)], ut[np.ix_(rows, cols)].astype(np.float64)
+        vc = oracle.anscombe(cc)
+        _, go = oracle.energy_grad(uc, vc, k.astype(np.float64), a.astype(np.float64),
+                                   np.float32(lam), data_term)
+        gp = oracle.grad_prior(uc, k.astype(np.float64), a.astype(np.float64))
+        scale = max(np.max(np.abs(gp)), np.max(np.abs(go - gp)), 1e-3)
+        ro, co = py - y0, px - x0
+        assert abs(gg[n] - go[ro, co]) <= 1e-4 * scale, ((py, px), gg[n], go[ro, co])
