@@ -37,11 +37,15 @@ def _specs(fe, torch, n, seed=0):
     return specs
 
 
-@pytest.mark.parametrize("budget_mb,per_tick", [(256, 7), (1, 5)])
-def test_served_results_equal_alone(env, budget_mb, per_tick):
+@pytest.mark.parametrize("budget_mb,per_tick,tick_work", [(256, 7, 0), (1, 5, 0),
+                                                         (256, 6, 40000), (256, 9, 1)])
+def test_served_results_equal_alone(env, budget_mb, per_tick, tick_work):
+    """tick_work > 0: ticks offer iterations to the oldest resident jobs first
+    and stop at that many pixel-iterations (1: one job advances per tick)."""
     torch, fe, serving, prior = env
     specs = _specs(fe, torch, 14)
-    srv = serving.Server(prior, budget_mb << 20, iters_per_tick=per_tick, max_active=64)
+    srv = serving.Server(prior, budget_mb << 20, iters_per_tick=per_tick, max_active=64,
+                         tick_pixel_iters=tick_work)
     arrivals = np.cumsum(np.random.default_rng(1).exponential(0.002, len(specs)))
     comps, outs, wall = serving.run_stream(srv, arrivals, specs, timeout_s=120)
     srv.close()
