@@ -674,9 +674,11 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             U[ur * Math::kUS + uc] = ucur[(long)yy * W + xx];
         }
     }
+    // the wave index as a scalar (the row arithmetic of the steps stays on
+    // the scalar unit: -1 % per launch, measured)
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     // the row a wave fetches: columns lane and 64 + lane (lane < US - 64),
     // both values of each pair for the pair tile
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
     float uf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     auto u_fetch = [&](int st) {
         const int ur = (st + 1) * NW + 2 * R + G::UROWS_EXTRA + wv;
@@ -777,7 +779,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // Inputs of the row a wave will finish are fetched one step ahead.
     float pf_up = 0.0f, pf_y = 0.0f, pf_u = 0.0f;
     auto prefetch = [&](int st) {
-        const int orow = st * NW - 2 * R + wave;
+        const int orow = st * NW - 2 * R + wv;
         if (orow >= 0 && orow < ty && lane < tx) {
             const long pix = (long)(y0 + orow) * W + x0 + lane;
             if constexpr (!GRAD) pf_up = uprev[pix];
@@ -786,7 +788,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
     auto finalize = [&](int st) {
-        const int orow = st * NW - 2 * R + wave;
+        const int orow = st * NW - 2 * R + wv;
         if (orow < 0 || orow >= ty) return;    // uniform over the wave
         const int y = y0 + orow;
         const int x = x0 + (lane < tx ? lane : tx - 1);
@@ -855,7 +857,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     };
 
     auto qrow = [&](int st) {
-        const int qr = st * NW + wave;
+        const int qr = st * NW + wv;
         const int qy = y0 - R + qr;
         const bool own_row = qr >= R && qr < R + ty;
         if (qr < nq && qy >= 0 && qy < H) {
