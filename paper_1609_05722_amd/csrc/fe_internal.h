@@ -37,7 +37,8 @@ fe_status validate_job_counts(int device, const fe_job *jobs, int n);
 // fe_advance_noalloc (one copy per device, kept until the process ends).
 constexpr size_t kNoallocScratchBytes = 256 * 1024;
 // Resolves the array's address on `device`, which must be current; once per
-// device (later calls return at once).  Called by fe_create.
+// device (later calls return at once; devices 64 and up keep none).  Called
+// by fe_create.
 hipError_t noalloc_setup(int device);
 // The array's device address on `device`, or NULL before noalloc_setup.
 void *noalloc_scratch(int device);
