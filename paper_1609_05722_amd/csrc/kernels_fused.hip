@@ -868,9 +868,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 // of blocks k - 1 .. k + 1, so it follows psi of block k + 1.
                 // Branch-free, two accumulators: the forward products of
                 // block k + 1 are issued before the influence of block k.
-                // (one accumulator where two would not fit the registers,
-                // and in the energy mode)
-                constexpr bool two = Math::kTwoAcc && !EN;
+                // (one accumulator where two would not fit the registers)
+                constexpr bool two = Math::kTwoAcc;
                 Acc acc1;
                 Acc &accb = two ? acc1 : acc;
                 forward(qr, 0, acc);
