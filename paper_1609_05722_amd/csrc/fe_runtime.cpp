@@ -777,7 +777,6 @@ fe_status fe_energy_grad_batch(const fe_ctx *c, const fe_grad_job *jobs, int32_t
 
 fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, size_t *bytes)
 {
-    fe_grad_job j{H, W, nullptr, nullptr, nullptr, 1.0f, FE_DATA_QUADRATIC};
     if (!bytes) return fail(FE_ERR_INVALID, "bytes is NULL");
     *bytes = 0;
     if (!c) return fail(FE_ERR_INVALID, "ctx is NULL");
@@ -785,7 +784,7 @@ fe_status fe_energy_grad_workspace_size(const fe_ctx *c, int32_t H, int32_t W, s
     if (H < 1 || W < 1 || H < r || W < r)
         return fail(FE_ERR_INVALID, "image %dx%d smaller than the filter radius %d", H, W, r);
     if ((long long)H * W > (1LL << 31) - 1) return fail(FE_ERR_INVALID, "image too large");
-    fe::GradItem it{j.height, j.width, nullptr, nullptr, nullptr, 1.0f, FE_DATA_QUADRATIC};
+    fe::GradItem it{H, W, nullptr, nullptr, nullptr, 1.0f, FE_DATA_QUADRATIC};
     *bytes = fe::grad_workspace_bytes(c->fused, &it, 1);
     return FE_OK;
 }
