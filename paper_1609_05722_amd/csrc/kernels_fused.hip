@@ -602,11 +602,18 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int g = lane >> 4;   // lane group: k index of the MFMA operands
 
     // ---- locate the tile: jobs are sorted by tile_base --------------------
-    int lo = 0, hi = njobs - 1;
+    // 64-way search: each lane reads the tile_base of one sample of the
+    // remaining range and a ballot counts the samples at or below the tile
+    // (sample 0 always is), so 64 jobs take one round of loads and 4096 two,
+    // instead of one dependent load per halving.
     const int bid = tile0 + (int)blockIdx.x;   // launches cover tiles tile0 ..
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_base <= bid) lo = mid; else hi = mid - 1;
+    int lo = 0, cnt = njobs;                   // the tile's job lies in [lo, lo + cnt)
+    while (cnt > 1) {
+        const int step = (cnt + 63) / 64;      // jobs per sample
+        const bool le = lane * step < cnt && jobs[lo + lane * step].tile_base <= bid;
+        const int k = __popcll(__ballot(le));
+        lo += (k - 1) * step;
+        cnt = min(step, cnt - (k - 1) * step);
     }
     const JobDesc J = jobs[lo];
     if (iter >= J.iters) return;
@@ -630,6 +637,53 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
     unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
 
+    // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
+    // (one more row and the two padding columns hold finite values that
+    // zero-weight taps of the padded BF16/FP16 layout may read).  Step st
+    // reads tile rows below (st + 1) NW + 2R + 1.  Where the registers allow
+    // (Math::kStreamU), the prologue loads the rows of step 0 and during step
+    // st wave w fetches tile row (st + 1) NW + 2R + 1 + w (loads issued at
+    // the start of the step, the row stored to LDS before its first
+    // barrier); otherwise the prologue loads the whole tile.
+    const int urows = ty + 4 * R + G::UROWS_EXTRA;
+    constexpr int kURow0 = NW + 2 * R + G::UROWS_EXTRA;   // rows step 0 reads
+    const int urows0 = Math::kStreamU ? min(urows, kURow0) : urows;
+    // Loads go out kUB per thread before their LDS stores, so that their
+    // latencies overlap (a load-store loop waits one latency per element).
+    // The first batch (all of it when the rows stream) is issued before the
+    // operand tables: the tables' many loads would otherwise queue ahead of
+    // it and its latency would follow theirs instead of overlapping them.
+    constexpr int kUB = 4;
+    const int nu = urows0 * Math::kUS;
+    float va[kUB], vb[kUB];
+    auto u_load = [&](int i0) {
+#pragma unroll
+        for (int j = 0; j < kUB; ++j) {
+            const int i = i0 + j * 64 * NW;
+            va[j] = vb[j] = 0.0f;
+            if (i < nu) {
+                const int ur = i / Math::kUS, uc = i - ur * Math::kUS;
+                const gfloat *row = ucur + (long)sym_clamp(y0 - 2 * R + ur, H) * W;
+                va[j] = row[sym_clamp(x0 - 2 * R + uc, W)];
+                if constexpr (Math::kPairTile) vb[j] = row[sym_clamp(x0 - 2 * R + uc + 1, W)];
+            }
+        }
+    };
+    auto u_put = [&](int i0) {
+#pragma unroll
+        for (int j = 0; j < kUB; ++j) {
+            const int i = i0 + j * 64 * NW;
+            if (i < nu) {
+                if constexpr (Math::kPairTile) U[i] = Math::pack_pair(va[j], vb[j]);
+                else U[i] = va[j];
+            }
+        }
+    };
+    u_load(threadIdx.x);
+
+    Math mth;
+    mth.load(t0, t1, t2, t3, lane, Tab);
+
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
     // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
     // block column xr + R; hoff: H offset of (a, xr); xrr: xr, or a value
@@ -646,33 +700,14 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         hoff[rr] = a * Math::kHS + xr;
         xrr[rr] = ok ? xr : -1000;
     }
-    Math mth;
-    mth.load(t0, t1, t2, t3, lane, Tab);
 
     // ---- zero this wave's scratch (its pad columns / rows stay zero) ------
     for (int i = lane; i < Math::kScratchFloats; i += 64) Sw[i] = 0.0f;
 
-    // ---- u tile: image rows y0-2R.., cols x0-2R.., symmetric extension ----
-    // (one more row and the two padding columns hold finite values that
-    // zero-weight taps of the padded BF16/FP16 layout may read).  Step st
-    // reads tile rows below (st + 1) NW + 2R + 1.  Where the registers allow
-    // (Math::kStreamU), the prologue loads the rows of step 0 and during step
-    // st wave w fetches tile row (st + 1) NW + 2R + 1 + w (loads issued at
-    // the start of the step, the row stored to LDS before its first
-    // barrier); otherwise the prologue loads the whole tile.
-    const int urows = ty + 4 * R + G::UROWS_EXTRA;
-    constexpr int kURow0 = NW + 2 * R + G::UROWS_EXTRA;   // rows step 0 reads
-    const int urows0 = Math::kStreamU ? min(urows, kURow0) : urows;
-    for (int i = threadIdx.x; i < urows0 * Math::kUS; i += 64 * NW) {
-        const int ur = i / Math::kUS, uc = i - ur * Math::kUS;
-        const int yy = sym_clamp(y0 - 2 * R + ur, H);
-        const int xx = sym_clamp(x0 - 2 * R + uc, W);
-        if constexpr (Math::kPairTile) {
-            const int xx1 = sym_clamp(x0 - 2 * R + uc + 1, W);
-            U[ur * Math::kUS + uc] = Math::pack_pair(ucur[(long)yy * W + xx], ucur[(long)yy * W + xx1]);
-        } else {
-            U[ur * Math::kUS + uc] = ucur[(long)yy * W + xx];
-        }
+    u_put(threadIdx.x);
+    for (int i0 = threadIdx.x + kUB * 64 * NW; i0 < nu; i0 += kUB * 64 * NW) {
+        u_load(i0);
+        u_put(i0);
     }
     // the wave index as a scalar (the row arithmetic of the steps stays on
     // the scalar unit: -1 % per launch, measured)
