@@ -167,6 +167,16 @@ constexpr int rows_limit()
     return rows < kMaxTileRows ? (int)rows : kMaxTileRows;
 }
 
+// Tile of workgroup i of n under the XCD-contiguous order: XCD x = i % 8
+// receives workgroups x, x + 8, ... and with them the tiles
+// [x q + min(x, r), ...) in order, q = n / 8, r = n % 8 (a bijection of 0..n-1).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int i, int n)
+{
+    const int x = i % kXcds, k = i / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ int sym_clamp(int i, int n)
 {
     if (i < 0) i = -1 - i;
@@ -606,7 +616,12 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // remaining range and a ballot counts the samples at or below the tile
     // (sample 0 always is), so 64 jobs take one round of loads and 4096 two,
     // instead of one dependent load per halving.
-    const int bid = tile0 + (int)blockIdx.x;   // launches cover tiles tile0 ..
+    // Launches cover tiles tile0 .. tile0 + gridDim.x - 1.  Workgroups go to
+    // the 8 XCDs in turn (workgroup i to XCD i % 8), each XCD with its own
+    // L2: XCD x takes one contiguous run of tiles, so that the tiles next to
+    // each other in a job (which read each other's halo rows and columns of
+    // u) share an L2.
+    const int bid = tile0 + xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, cnt = njobs;                   // the tile's job lies in [lo, lo + cnt)
     while (cnt > 1) {
         const int step = (cnt + 63) / 64;      // jobs per sample
@@ -1477,6 +1492,13 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         for (int i = 0; i < n; ++i)
             if (items[i].job->precision == prec && items[i].count > 0) grp.push_back(items[i]);
         if (grp.empty()) continue;
+        // Jobs in order of decreasing iteration count: at iteration it the
+        // jobs still running are a prefix of the table, and the launch covers
+        // just their tiles (no workgroups that return at once, and every XCD
+        // gets its share of the running tiles).
+        std::stable_sort(grp.begin(), grp.end(), [](const AdvanceItem &a, const AdvanceItem &b) {
+            return a.count > b.count;
+        });
         const int gn = (int)grp.size();
         Plan plan;
         TileChoice ch = forced;
@@ -1488,6 +1510,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         JobDesc *dj = table + slot;
         slot += gn;
         int max_it = 0, base = 0;
+        std::vector<long> first_tile(gn + 1, 0);   // tile_base of job i; [gn] = all tiles
         for (int c0 = 0; c0 < gn; c0 += kChunk) {
             JobChunk jc{};
             jc.first = c0;
@@ -1506,6 +1529,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
                 d.nty = plan.jobs_nty[c0 + i];
                 d.tile_base = base;
                 base += d.ntx * d.nty;
+                first_tile[c0 + i + 1] = base;
                 d.iters = it.count;
                 d.it0 = it.done;
                 d.tau = j.tau;
@@ -1521,15 +1545,20 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        // a launch covers at most kMaxLaunchTiles workgroups (its work-item
-        // count stays below 2^31)
-        for (int it = 0; it < max_it; ++it)
-            for (long t0 = 0; t0 < plan.ntiles; t0 += kMaxLaunchTiles) {
-                const int nb = (int)std::min<long>(kMaxLaunchTiles, plan.ntiles - t0);
+        // Iteration it runs the jobs [0, k) with count > it, tiles
+        // [0, first_tile[k]); a launch covers at most kMaxLaunchTiles
+        // workgroups (its work-item count stays below 2^31).
+        int k = gn;
+        for (int it = 0; it < max_it; ++it) {
+            while (k > 0 && grp[k - 1].count <= it) --k;
+            const long active = first_tile[k];
+            for (long t0 = 0; t0 < active; t0 += kMaxLaunchTiles) {
+                const int nb = (int)std::min<long>(kMaxLaunchTiles, active - t0);
                 hipError_t e = launch_any(prec, plan.waves, bank, dj, gn, nb, (int)t0, it,
                                           plan.tile_h, s);
                 if (e != hipSuccess) return e;
             }
+        }
     }
     return hipSuccess;
 }
