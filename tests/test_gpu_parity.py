@@ -140,16 +140,18 @@ def test_full_size_fp32(fe, torch, peak):
 
 
 def test_batch_equals_alone_and_is_deterministic(fe, torch):
-    """Jobs of different sizes and data terms in one call give bitwise the
-    same results as each job alone, and repeated runs are bitwise equal."""
+    """Jobs of different sizes, data terms and iteration counts in one call
+    give bitwise the same results as each job alone (the launches of the
+    later iterations cover only the jobs still running), and repeated runs
+    are bitwise equal."""
     prior, k, a = _prior(fe, 7, 48)
     tau, gamma = step_size_for(7, 48)
-    shapes = [(64, 64, 1.0), (97, 130, 8.0), (20, 300, 2.0), (256, 256, 4.0)]
+    shapes = [(64, 64, 1.0, 25), (97, 130, 8.0, 7), (20, 300, 2.0, 40), (256, 256, 4.0, 13)]
     specs, ys = [], []
-    for i, (H, W, pk) in enumerate(shapes):
+    for i, (H, W, pk, its) in enumerate(shapes):
         _, y = noisy_pair(300 + i, 400 + i, H, W, pk)
         ys.append(y)
-        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, 25, tau, gamma,
+        specs.append(fe.JobSpec(torch.from_numpy(y).cuda(), 40.0, its, tau, gamma,
                                 data_term="auto", peak=pk, want_anscombe=True))
     mix = fe.denoise_jobs(prior, specs)
     mix2 = fe.denoise_jobs(prior, specs)
