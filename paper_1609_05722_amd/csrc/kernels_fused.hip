@@ -80,6 +80,7 @@ constexpr int kWavesF32 = 8, kWavesP16 = 12;
 constexpr int kDefaultWavesF32 = 8;
 constexpr int kQB = 4;                // 16-pixel blocks per q-row
 constexpr int kQW = 16 * kQB;         // q-row width (pixels)
+constexpr int kRingSpins = 1 << 20;   // bound of a ring_wait (polls of ~100 cycles)
 
 // Per-job description the step kernel reads.
 struct JobDesc {
@@ -146,7 +147,7 @@ constexpr size_t lds_fixed_floats()
     using G = Geo<M>;
     return (size_t)Math::kNW * Math::kScratchFloats +
            (size_t)Ring<M, Math::kNW, Math::kTwo>::HR * M * Math::kHS + Math::kTabFloats +
-           (MODE == kGradEnergy ? kAlphaFloats : 0);
+           (MODE == kGradEnergy ? kAlphaFloats : 0) + (Math::kTwo ? Math::kNW : 0);
 }
 
 template <int M, typename Math, int MODE = kStep>
@@ -649,6 +650,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
     float *Tab = Hr + (size_t)HR * M * Math::kHS;          // the policy's tables
     float *Al = Tab + Math::kTabFloats;                    // alpha_i (energy mode)
+    // two-barrier variants: per-wave count of finished output-row phases
+    int *fdone = (int *)(Al + (MODE == kGradEnergy ? kAlphaFloats : 0));
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
     unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
 
@@ -759,6 +762,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
     if constexpr (EN)
         if (threadIdx.x < kAlphaFloats) Al[threadIdx.x] = alpha[threadIdx.x];
+    if constexpr (Math::kTwo)
+        if (threadIdx.x < NW) fdone[threadIdx.x] = 0;
     // per-lane partial energies of the pixels this tile owns (energy mode)
     float e_prior = 0.0f, e_data = 0.0f;
     // Every global load of the prologue (operand tables, u tile) has landed:
@@ -906,6 +911,35 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
 
+    // Two-barrier variants: the second barrier of a step is replaced by a
+    // wait, right before a q-row's first write into the H ring, for the
+    // output rows that still read the slot it overwrites.  q-row
+    // qr = st NW + w takes the slot of q-row qr - (NW + 2R), which only the
+    // output rows finished in step st - 1 by waves w - 2R .. w read (older
+    // readers finished before the step's first barrier).  A wave's count in
+    // fdone is the number of its output-row phases finished; the spin is
+    // bounded (a wave that gives up goes on; results would then be wrong,
+    // but every wave ends).
+    auto ring_wait = [&](int st) {
+        if constexpr (Math::kTwo) {
+            if (st == 0) return;
+            for (int spin = 0; spin < kRingSpins; ++spin) {
+                int ok = 1;
+                if (lane < NW && lane >= wv - 2 * R && lane <= wv)
+                    ok = __hip_atomic_load(fdone + lane, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP) >= st;
+                if (__all(ok)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        }
+    };
+    auto ring_release = [&](int st) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        if (lane == 0)
+            __hip_atomic_store(fdone + wv, st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+
     auto qrow = [&](int st) {
         const int qr = st * NW + wv;
         const int qy = y0 - R + qr;
@@ -928,6 +962,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 if (!two) forward(qr, 1, accb);
                 if (two) forward(qr, 2, acc);
                 adjoint(1, accb, own_row);
+                ring_wait(st);
                 lds_order();
                 mth.gather(Pw, Hs, 0, p, g);
                 if (!two) forward(qr, 2, acc);
@@ -950,6 +985,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
                 for (int k = 1; k < kQB; ++k) {
                     lds_order();
                     forward(qr, k, acc);
+                    if (k == 1 && Math::kTwo) ring_wait(st);
                     collapse(Hs, k - 1);
                     lds_order();
                     adjoint(k, acc, own_row);
@@ -963,7 +999,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     if constexpr (Math::kTwo) {
         // Step st: q-row st * NW + wave, barrier, then the output rows whose
-        // q-rows are now complete, barrier (the ring needs NW + 2R slots).
+        // q-rows are now complete (the ring needs NW + 2R slots; the next
+        // q-row's first ring write waits for the output rows that read the
+        // slot it takes: ring_wait).
         for (int st = 0; st < nsteps; ++st) {
             prefetch(st);
             u_fetch(st);
@@ -971,7 +1009,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             u_store(st);
             lds_barrier();
             finalize(st);
-            lds_barrier();
+            ring_release(st);
         }
     } else {
         // Step st: finish the output rows of step st - 1, then run q-row
@@ -991,8 +1029,9 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     }
     if constexpr (EN) {
         // The workgroup's partial energies: lanes, then waves, in a fixed
-        // order (the loop's last barrier has retired every LDS read, so the
-        // u tile's first floats are free).
+        // order (after a barrier that retires every LDS read of the steps,
+        // the u tile's first floats are free).
+        lds_barrier();
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             e_prior += __shfl_xor(e_prior, o);
