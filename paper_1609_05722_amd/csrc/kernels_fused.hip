@@ -69,6 +69,8 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(1))) float gfloat;
 // LDS quad: 16-byte reads through it compile to ds_read_b128.
 typedef __attribute__((address_space(3))) f32x4 lquad;
+typedef __attribute__((address_space(3))) float lfloat;
+typedef __attribute__((address_space(3))) u32x4 lu32x4;
 typedef __attribute__((address_space(3))) u32x2 lpair;
 
 // Waves per workgroup: FP32 is built for 8 (every operand in registers,
@@ -260,11 +262,19 @@ struct MathF32 {
         }
     }
 
+    // 32-bit words of the operand tables t0 .. t3 (the layouts above)
+    static constexpr int tab_words(int i)
+    {
+        return i == 0 ? G::KF * NFB * 64 : i == 1 ? NFB * 4 * G::NTB * 64 : NFB * 4 * 64;
+    }
+    // FL: the tables are read from an LDS copy (same layout) instead of HBM
+    template <bool FL = false>
     __device__ void load(const void *t0, const void *t1, const void *t2, const void *t3,
                          int lane, const float *tab)
     {
-        const float *fwd_tab = (const float *)t0, *adj_tab = (const float *)t1;
-        const float *lastf_tab = (const float *)t2, *lasta_tab = (const float *)t3;
+        using TP = std::conditional_t<FL, const lfloat *, const float *>;
+        const TP fwd_tab = (TP)t0, adj_tab = (TP)t1;
+        const TP lastf_tab = (TP)t2, lasta_tab = (TP)t3;
         const int p = lane & 15, g = lane >> 4;
 #pragma unroll
         for (int s = 0; s < G::KF; ++s)
@@ -472,10 +482,18 @@ struct MathP16 {
         return __builtin_bit_cast(float, w);
     }
 
+    // 32-bit words of the operand tables t0, t1 (the layouts above)
+    static constexpr int tab_words(int i)
+    {
+        return i == 0 ? KS * NFB * 64 * 4 : i == 1 ? KG * 64 * 4 : 0;
+    }
+    // FL: the tables are read from an LDS copy (same layout) instead of HBM
+    template <bool FL = false>
     __device__ void load(const void *t0, const void *t1, const void *, const void *, int lane,
                          const float *)
     {
-        const u32x4 *fwd_tab = (const u32x4 *)t0, *adj_tab = (const u32x4 *)t1;
+        using TP = std::conditional_t<FL, const lu32x4 *, const u32x4 *>;
+        const TP fwd_tab = (TP)t0, adj_tab = (TP)t1;
         const int p = lane & 15, g = lane >> 4;
 #pragma unroll
         for (int s = 0; s < KS; ++s)
@@ -699,8 +717,35 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     };
     u_load(threadIdx.x);
 
+    // ---- operand tables ----------------------------------------------------
+    // Every wave needs the same per-lane tables in registers.  Where they fit
+    // the H ring (unused until step 0) and the policy keeps none in LDS, the
+    // workgroup reads them from HBM once, cooperatively, into the ring, and
+    // the waves load their registers from there: one pass through the vector
+    // L1 instead of one per wave (the L1 bandwidth bounded the per-wave reads).
+    constexpr int kTw0 = Math::tab_words(0), kTw1 = Math::tab_words(1),
+                  kTw2 = Math::tab_words(2), kTw3 = Math::tab_words(3);
+    constexpr int kTq = (kTw0 + kTw1 + kTw2 + kTw3) / 4;     // 16-byte quads
+    constexpr bool kStageTabs = Math::kTabFloats == 0 && kTq * 4 <= HR * M * Math::kHS &&
+                                kTw0 % 4 == 0 && kTw1 % 4 == 0 && kTw2 % 4 == 0;
+    constexpr int kTqPer = (kTq + 64 * NW - 1) / (64 * NW);
+    u32x4 tq[kStageTabs ? kTqPer : 1];
+    if constexpr (kStageTabs) {
+#pragma unroll
+        for (int j = 0; j < kTqPer; ++j) {
+            const int q = threadIdx.x + j * 64 * NW;
+            if (q < kTq) {
+                const u32x4 *src = q < kTw0 / 4 ? (const u32x4 *)t0 + q
+                                   : q < (kTw0 + kTw1) / 4 ? (const u32x4 *)t1 + (q - kTw0 / 4)
+                                   : q < (kTw0 + kTw1 + kTw2) / 4
+                                       ? (const u32x4 *)t2 + (q - (kTw0 + kTw1) / 4)
+                                       : (const u32x4 *)t3 + (q - (kTw0 + kTw1 + kTw2) / 4);
+                tq[j] = *(const __attribute__((address_space(1))) u32x4 *)src;
+            }
+        }
+    }
     Math mth;
-    mth.load(t0, t1, t2, t3, lane, Tab);
+    if constexpr (!kStageTabs) mth.load(t0, t1, t2, t3, lane, Tab);
 
     // Collapse tasks of this lane, round rr: (a, xr) with task = 64 rr + lane
     // = a * XSPAN + xr + R.  sbase: scratch offset of tap (a, 0) at the
@@ -723,6 +768,17 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     for (int i = lane; i < Math::kScratchFloats; i += 64) Sw[i] = 0.0f;
 
     u_put(threadIdx.x);
+    if constexpr (kStageTabs) {
+        u32x4 *Hq = (u32x4 *)Hr;
+#pragma unroll
+        for (int j = 0; j < kTqPer; ++j) {
+            const int q = threadIdx.x + j * 64 * NW;
+            if (q < kTq) Hq[q] = tq[j];
+        }
+        lds_barrier();
+        mth.template load<true>(Hr, Hr + kTw0, Hr + kTw0 + kTw1, Hr + kTw0 + kTw1 + kTw2, lane,
+                                Tab);
+    }
     for (int i0 = threadIdx.x + kUB * 64 * NW; i0 < nu; i0 += kUB * 64 * NW) {
         u_load(i0);
         u_put(i0);
