@@ -1072,7 +1072,12 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             qrow(st);
             u_store(st);
             lds_barrier();
+            // the output rows (vector work that the waves waiting in ring_wait
+            // depend on) at the highest issue priority of the step (-1 % per
+            // launch, measured)
+            __builtin_amdgcn_s_setprio(2);
             finalize(st);
+            __builtin_amdgcn_s_setprio(0);
             ring_release(st);
         }
     } else {
