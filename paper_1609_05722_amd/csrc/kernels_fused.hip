@@ -129,8 +129,10 @@ struct Geo {
 };
 
 // H ring slots: with one barrier per pipeline step the rows being finished
-// (2R + NW q-rows) and the NW rows being written coexist; with two barriers
-// per step they do not.
+// (2R + NW q-rows) and the NW rows being written coexist; in the TWO form
+// (a barrier between a step's q-rows and its output rows, and a wait before
+// a q-row's first ring write for the output rows that still read the slot)
+// they do not.
 template <int M, int NW, bool TWO>
 struct Ring {
     static constexpr int HR = TWO ? NW + (M - 1) : 2 * NW + (M - 1);
@@ -214,8 +216,8 @@ __device__ __forceinline__ void lds_barrier()
 // per SIMD), one barrier per pipeline step.  LDS = true: 12 waves (three per
 // SIMD); the adjoint operands and both last-tap tables live in LDS, one row
 // of 16-byte aligned floats per lane (row strides of 4 mod 8 floats keep the
-// 16-byte reads of eight consecutive lanes on distinct banks); two barriers
-// per step.
+// 16-byte reads of eight consecutive lanes on distinct banks); the TWO form of
+// the pipeline (see Ring).
 constexpr int odd_quads(int n) { return ((n + 3) / 4) % 2 ? (n + 3) / 4 * 4 : (n + 3) / 4 * 4 + 4; }
 
 template <int M, int NFB, bool LDS>
@@ -676,7 +678,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     float *Hr = S + (size_t)NW * Math::kScratchFloats;     // HR x M x QW
     float *Tab = Hr + (size_t)HR * M * Math::kHS;          // the policy's tables
     float *Al = Tab + Math::kTabFloats;                    // alpha_i (energy mode)
-    // two-barrier variants: per-wave count of finished output-row phases
+    // TWO form of the pipeline: per-wave count of finished output-row phases
     int *fdone = (int *)(Al + (MODE == kGradEnergy ? kAlphaFloats : 0));
     float *Sw = S + (size_t)wave * Math::kScratchFloats;
     unsigned short *Pw = (unsigned short *)Sw;             // psi scratch (gather form)
@@ -975,7 +977,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
 
-    // Two-barrier variants: the second barrier of a step is replaced by a
+    // TWO form of the pipeline: instead of a second barrier per step, a
     // wait, right before a q-row's first write into the H ring, for the
     // output rows that still read the slot it overwrites.  q-row
     // qr = st NW + w takes the slot of q-row qr - (NW + 2R), which only the
