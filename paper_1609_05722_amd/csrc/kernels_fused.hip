@@ -983,9 +983,12 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     // qr = st NW + w takes the slot of q-row qr - (NW + 2R), which only the
     // output rows finished in step st - 1 by waves w - 2R .. w read (older
     // readers finished before the step's first barrier).  A wave's count in
-    // fdone is the number of its output-row phases finished; the spin is
-    // bounded (a wave that gives up goes on; results would then be wrong,
-    // but every wave ends).
+    // fdone is the number of its output-row phases finished.  The waited-for
+    // waves belong to the workgroup and reach their release (after their
+    // output rows) without waiting on anything but the step's barrier, which
+    // this wave has passed, so the wait ends.  The spin is bounded all the
+    // same (at ~0.1 s, far beyond any real wait; a wave that gave up would go
+    // on with wrong results, but every wave ends).
     auto ring_wait = [&](int st) {
         if constexpr (Math::kTwo) {
             if (st == 0) return;
