@@ -508,7 +508,7 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": "fused_step_kernel<7,MathF32<7,3,false>,0> (8 waves; one launch = one "
+                     "kernel": "fused_step_kernel<7,MathF32<7,3,true>,0> (12 waves; one launch = one "
                                "iteration of all %d jobs)" % n,
                      "launch_us": round(launch_ms * 1e3, 2),
                      "flop_per_launch": flops_per_px_it(m, nf) * px_per_launch},

@@ -82,6 +82,11 @@ std::vector<int> tile_candidates(const FusedBank &bank, int prec, const AdvanceI
 // Waves per workgroup the step is built for: default_waves(prec) unless a
 // measured choice says otherwise; wave_options lists every variant.
 int default_waves(int prec);
+// default_waves(prec) where its variant exists for the bank, else the other one
+int bank_default_waves(const FusedBank &bank, int prec);
+// the waves a batch runs with when no measured choice exists (FP32: 12 on
+// tiles of at least six pipeline steps, else 8)
+int plan_waves(const FusedBank &bank, int prec, const AdvanceItem *items, int n);
 std::vector<int> wave_options(int prec);
 // Tallest tile the variant's LDS allows (0 if no such variant).
 int max_tile_rows(const FusedBank &bank, int prec, int nw);

@@ -76,10 +76,13 @@ typedef __attribute__((address_space(3))) u32x2 lpair;
 // Waves per workgroup: FP32 is built for 8 (every operand in registers,
 // two waves per SIMD, u tile rows streamed during the steps) and 12
 // (adjoint tables in LDS, three per SIMD, whole u tile in the prologue);
-// 8 is the default (measured slightly faster once its rows stream), the
-// tuner may pick either.  BF16/FP16 are built for 12 (three per SIMD).
+// 12 is the default for launches that fill the GPU (measured 0.9 % faster
+// on 4 x 512^2 since its second barrier per step became a ring-slot wait;
+// plan_waves), the tuner may pick either.
+// BF16/FP16 are built for 12 (three per SIMD).
 constexpr int kWavesF32 = 8, kWavesP16 = 12;
-constexpr int kDefaultWavesF32 = 8;
+constexpr int kDefaultWavesF32 = 12;
+constexpr int kMinSteps12 = 6;        // see plan_waves
 constexpr int kQB = 4;                // 16-pixel blocks per q-row
 constexpr int kQW = 16 * kQB;         // q-row width (pixels)
 constexpr int kRingSpins = 1 << 20;   // bound of a ring_wait (polls of ~100 cycles)
@@ -729,15 +732,17 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
 
     // ---- operand tables ----------------------------------------------------
     // Every wave needs the same per-lane tables in registers.  Where they fit
-    // the H ring (unused until step 0) and the policy keeps none in LDS, the
-    // workgroup reads them from HBM once, cooperatively, into the ring, and
+    // the H ring (unused until step 0), the workgroup reads them from HBM
+    // once, cooperatively, into the ring, and
     // the waves load their registers from there: one pass through the vector
     // L1 instead of one per wave (the L1 bandwidth bounded the per-wave reads).
+    // (a policy that keeps t1 .. t3 in LDS itself stages t0 only)
     constexpr int kTw0 = Math::tab_words(0), kTw1 = Math::tab_words(1),
                   kTw2 = Math::tab_words(2), kTw3 = Math::tab_words(3);
-    constexpr int kTq = (kTw0 + kTw1 + kTw2 + kTw3) / 4;     // 16-byte quads
-    constexpr bool kStageTabs = Math::kTabFloats == 0 && kTq * 4 <= HR * M * Math::kHS &&
-                                kTw0 % 4 == 0 && kTw1 % 4 == 0 && kTw2 % 4 == 0;
+    constexpr bool kOwnTabs = Math::kTabFloats != 0;
+    constexpr int kTq = (kOwnTabs ? kTw0 : kTw0 + kTw1 + kTw2 + kTw3) / 4;   // 16-byte quads
+    constexpr bool kStageTabs = kTq * 4 <= HR * M * Math::kHS && kTw0 % 4 == 0 &&
+                                (kOwnTabs || (kTw1 % 4 == 0 && kTw2 % 4 == 0));
     constexpr int kTqPer = (kTq + 64 * NW - 1) / (64 * NW);
     u32x4 tq[kStageTabs ? kTqPer : 1];
     if constexpr (kStageTabs) {
@@ -1589,6 +1594,20 @@ void make_plan(const FusedBank &bank, int prec, const AdvanceItem *items, int n,
     }
 }
 
+// Waves per workgroup when no measured choice exists.  FP32 runs its
+// 12-wave variant where its cost-model tiles take at least kMinSteps12
+// pipeline steps, else the 8-wave one: on short tiles (small images spread
+// over the CUs) the 12-wave prologue (whole u tile, LDS-resident tables) is
+// not amortised (measured on single-image serving: 64 vs 62 images/s).
+int plan_waves(const FusedBank &bank, int prec, const AdvanceItem *items, int n)
+{
+    const int nw = bank_default_waves(bank, prec);
+    if (prec != FE_PREC_FP32 || nw != 12 || max_tile_rows(bank, prec, 8) <= 0) return nw;
+    Plan p;
+    make_plan(bank, prec, items, n, &p, 12, 0);
+    return (p.tile_h + bank.m - 1 + 11) / 12 >= kMinSteps12 ? 12 : 8;
+}
+
 size_t Plan::device_bytes() const { return (size_t)std::max(njobs, 1) * sizeof(JobDesc); }
 size_t fused_table_bytes(int n) { return (size_t)std::max(n, 1) * sizeof(JobDesc); }
 
@@ -1617,7 +1636,7 @@ hipError_t run_fused(const FusedBank &bank, const AdvanceItem *items, int n, voi
         TileChoice ch = forced;
         if (ch.waves <= 0 && ch.ty <= 0 && tune) ch = tune->lookup(batch_key(prec, grp.data(), gn));
         if (ch.waves <= 0 || max_tile_rows(bank, prec, ch.waves) <= 0)
-            ch.waves = bank_default_waves(bank, prec);
+            ch.waves = plan_waves(bank, prec, grp.data(), gn);
         make_plan(bank, prec, grp.data(), gn, &plan, ch.waves, ch.ty);
         if (plan.ntiles > INT_MAX) return hipErrorInvalidValue;   // tile indices are ints
         JobDesc *dj = table + slot;

@@ -42,7 +42,25 @@ static void limits()
     // 64 filters of 7 x 7 do not fit three waves per SIMD in FP32
     CHECK(fe::max_tile_rows(bank(7, 64), FE_PREC_FP32, 12) == 0);
     CHECK(fe::max_tile_rows(bank(7, 64), FE_PREC_FP32, 8) > 0);
-    CHECK(fe::default_waves(FE_PREC_FP32) == 8 && fe::default_waves(FE_PREC_FP16) == 12);
+    CHECK(fe::default_waves(FE_PREC_FP32) == 12 && fe::default_waves(FE_PREC_FP16) == 12);
+    // where the 12-wave FP32 variant does not fit, the default falls back to 8
+    CHECK(fe::bank_default_waves(b7, FE_PREC_FP32) == 12);
+    CHECK(fe::bank_default_waves(bank(7, 64), FE_PREC_FP32) == 8);
+    // FP32 runs 12 waves on tall tiles (4 x 512^2: 74 rows, 7 steps), 8 on
+    // short ones (one 512^2 image spread over the CUs); BF16 / FP16 always 12
+    {
+        std::vector<fe_job> jb(4);
+        std::vector<fe::AdvanceItem> it(4);
+        for (int i = 0; i < 4; ++i) {
+            jb[i] = fe_job{};
+            jb[i].height = jb[i].width = 512;
+            it[i] = {&jb[i], nullptr, 0, 10};
+        }
+        CHECK(fe::plan_waves(b7, FE_PREC_FP32, it.data(), 4) == 12);
+        CHECK(fe::plan_waves(b7, FE_PREC_FP32, it.data(), 1) == 8);
+        CHECK(fe::plan_waves(b7, FE_PREC_BF16, it.data(), 1) == 12);
+        CHECK(fe::plan_waves(bank(7, 64), FE_PREC_FP32, it.data(), 4) == 8);
+    }
     const std::vector<int> w = fe::wave_options(FE_PREC_FP32);
     CHECK(w.size() == 2 && std::count(w.begin(), w.end(), 8) == 1 &&
           std::count(w.begin(), w.end(), 12) == 1);
