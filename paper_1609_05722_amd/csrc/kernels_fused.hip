@@ -644,16 +644,16 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
     const int g = lane >> 4;   // lane group: k index of the MFMA operands
 
     // ---- locate the tile: jobs are sorted by tile_base --------------------
-    // 64-way search: each lane reads the tile_base of one sample of the
-    // remaining range and a ballot counts the samples at or below the tile
-    // (sample 0 always is), so 64 jobs take one round of loads and 4096 two,
-    // instead of one dependent load per halving.
     // Launches cover tiles tile0 .. tile0 + gridDim.x - 1.  Workgroups go to
     // the 8 XCDs in turn (workgroup i to XCD i % 8), each XCD with its own
     // L2: XCD x takes one contiguous run of tiles, so that the tiles next to
     // each other in a job (which read each other's halo rows and columns of
     // u) share an L2.
     const int bid = tile0 + xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    // 64-way search: each lane reads the tile_base of one sample of the
+    // remaining range and a ballot counts the samples at or below the tile
+    // (sample 0 always is), so 64 jobs take one round of loads and 4096 two,
+    // instead of one dependent load per halving.
     int lo = 0, cnt = njobs;                   // the tile's job lies in [lo, lo + cnt)
     while (cnt > 1) {
         const int step = (cnt + 63) / 64;      // jobs per sample
