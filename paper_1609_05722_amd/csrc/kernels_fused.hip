@@ -538,10 +538,11 @@ struct MathP16 {
     {
 #pragma unroll
         for (int fb = 0; fb < NFB; ++fb) a.z[fb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // while a wave issues its products its issue priority is raised, so
-        // that the matrix pipe is fed ahead of the other waves' vector work
-        // (BF16 and FP16 products overlap vector instructions of other waves;
-        // -1 % per launch, measured)
+        // while a wave issues its forward products its issue priority is
+        // raised, so that the matrix pipe is fed ahead of the other waves'
+        // vector work (BF16 and FP16 products overlap vector instructions of
+        // other waves; -1 % per launch, measured; the same around the gather
+        // products measured no better)
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -602,7 +603,7 @@ struct MathP16 {
 #pragma unroll
         for (int s = 0; s < KG; ++s) w[s] = *(const lquad *)(base + aoff[s]);
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
-        __builtin_amdgcn_s_setprio(1);   // as in forward()
+
 #pragma unroll
         for (int s = 0; s < KG; ++s)
             d = mfma(__builtin_bit_cast(vec8, w[s]), __builtin_bit_cast(vec8, bgat[s]), d);
@@ -610,7 +611,6 @@ struct MathP16 {
         // otherwise sink each read to its product and expose its latency)
         __builtin_amdgcn_sched_group_barrier(0x0100, KG, 0);   // LDS reads
         __builtin_amdgcn_sched_group_barrier(0x0008, KG, 0);   // MFMA
-        __builtin_amdgcn_s_setprio(0);
         if (p < M) *(f32x4 *)(Hs + p * kHS + 16 * k + 4 * g) = d;
     }
 
