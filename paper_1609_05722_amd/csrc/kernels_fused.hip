@@ -250,19 +250,48 @@ struct MathF32 {
     };
 
     // LDS copies of the adjoint and last-tap tables (all threads; the
-    // caller's barrier publishes them).
-    static __device__ void stage(float *tab, const void *t1, const void *t2, const void *t3,
-                                 int tid, int nthreads)
+    // caller's barrier publishes them), in two parts: the loads early in
+    // the prologue, all in flight at once, the LDS stores later.
+    static constexpr int kStA = LDS ? (64 * NA + 64 * kNW - 1) / (64 * kNW) : 1;
+    static constexpr int kStL = LDS ? (64 * NFB * 4 + 64 * kNW - 1) / (64 * kNW) : 1;
+    struct Staged {
+        float a[kStA], f[kStL], l[kStL];
+    };
+    static __device__ void stage_load(Staged &r, const void *t1, const void *t2, const void *t3,
+                                      int tid)
     {
         if constexpr (LDS) {
-            const float *adj = (const float *)t1, *lf = (const float *)t2,
-                        *la = (const float *)t3;
-            for (int i = tid; i < 64 * NA; i += nthreads)
-                tab[(i & 63) * SA + (i >> 6)] = adj[i];
+            const gfloat *adj = (const gfloat *)t1, *lf = (const gfloat *)t2,
+                         *la = (const gfloat *)t3;
+#pragma unroll
+            for (int j = 0; j < kStA; ++j) {
+                const int i = tid + j * 64 * kNW;
+                r.a[j] = i < 64 * NA ? adj[i] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < kStL; ++j) {
+                const int i = tid + j * 64 * kNW;
+                r.f[j] = i < 64 * NFB * 4 ? lf[i] : 0.0f;
+                r.l[j] = i < 64 * NFB * 4 ? la[i] : 0.0f;
+            }
+        }
+    }
+    static __device__ void stage_store(float *tab, const Staged &r, int tid)
+    {
+        if constexpr (LDS) {
+#pragma unroll
+            for (int j = 0; j < kStA; ++j) {
+                const int i = tid + j * 64 * kNW;
+                if (i < 64 * NA) tab[(i & 63) * SA + (i >> 6)] = r.a[j];
+            }
             float *tf = tab + 64 * SA, *tl = tf + 64 * SL;
-            for (int i = tid; i < 64 * NFB * 4; i += nthreads) {
-                tf[(i & 63) * SL + (i >> 6)] = lf[i];
-                tl[(i & 63) * SL + (i >> 6)] = la[i];
+#pragma unroll
+            for (int j = 0; j < kStL; ++j) {
+                const int i = tid + j * 64 * kNW;
+                if (i < 64 * NFB * 4) {
+                    tf[(i & 63) * SL + (i >> 6)] = r.f[j];
+                    tl[(i & 63) * SL + (i >> 6)] = r.l[j];
+                }
             }
         }
     }
@@ -476,7 +505,9 @@ struct MathP16 {
         f32x4 z[NFB];
     };
 
-    static __device__ void stage(float *, const void *, const void *, const void *, int, int) {}
+    struct Staged {};
+    static __device__ void stage_load(Staged &, const void *, const void *, const void *, int) {}
+    static __device__ void stage_store(float *, const Staged &, int) {}
 
     // The pair tile's word: lo = P(a), hi = P(b), each rounded to nearest even.
     static __device__ __forceinline__ float pack_pair(float a, float b)
@@ -729,6 +760,8 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
         }
     };
     u_load(threadIdx.x);
+    typename Math::Staged staged;
+    Math::stage_load(staged, t1, t2, t3, threadIdx.x);
 
     // ---- operand tables ----------------------------------------------------
     // Every wave needs the same per-lane tables in registers.  Where they fit
@@ -830,7 +863,7 @@ void fused_step_kernel(const JobDesc *__restrict__ jobs, int njobs,
             }
         }
     };
-    Math::stage(Tab, t1, t2, t3, threadIdx.x, 64 * NW);
+    Math::stage_store(Tab, staged, threadIdx.x);
     if constexpr (EN)
         if (threadIdx.x < kAlphaFloats) Al[threadIdx.x] = alpha[threadIdx.x];
     if constexpr (Math::kTwo)
